@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark of the swept-rule hot path on one MI355X.
+
+One benchmark step is one full solve of the workload through the C ABI
+(``swept_solve``): every phase of the swept schedule -- Up Triangle,
+Diamonds, Down Triangle -- over the whole grid for all its time steps.  The
+default workload is the 1D heat equation (FTCS, binary64) on 2^22 periodic
+cells, r = 1/4, seeded random-mode initial condition, 20000 time steps.
+
+Prints ONE JSON line: the swept throughput in cell-updates/s (value), the
+classic one-launch-per-step throughput on the same workload, the roofline
+of the dominant kernel (timed live with HIP events on the library's stream)
+and the plain CPU oracle timed on a bounded sample of the same workload.
+Inputs are resident in HBM before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_1811_08282_amd as sw  # noqa: E402
+from paper_1811_08282_amd import workloads as wl  # noqa: E402
+
+METRIC = "cell-updates/s swept vs naive (FP64, FP32) at stated error; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6  # counts an FMA as two flops
+
+WORKLOADS = {
+    "heat_f64_large": (wl.HEAT_LARGE, sw.HEAT_F64),
+    "heat_f64_small": (wl.HEAT_SMALL, sw.HEAT_F64),
+    "euler_f64_large": (wl.EULER_LARGE, sw.EULER_F64),
+    "heat_f32_prec": (wl.HEAT_PREC, sw.HEAT_F32),
+    "euler_f32_prec": (wl.EULER_PREC, sw.EULER_F32),
+    "heat_f64_prec": (wl.HEAT_PREC, sw.HEAT_F64),
+    "euler_f64_prec": (wl.EULER_PREC, sw.EULER_F64),
+}
+
+# algorithmic bytes of the swept working struct per cell (read + write per phase)
+STRUCT_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 12, sw.EULER_F64: 56, sw.EULER_F32: 44}
+# algorithmic HBM bytes per cell-update of the classic path
+NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32: 140}
+# binary64 operations per cell-update (no fused multiply-add)
+HEAT_FLOPS = 5
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pack_state(eq, q):
+    q = np.asarray(q, np.float64)
+    if eq == sw.HEAT_F64:
+        return q.reshape(1, -1)
+    if eq == sw.HEAT_F32:
+        return np.stack([q.astype(np.float32), np.zeros(q.shape, np.float32)])
+    if eq == sw.EULER_F64:
+        return q
+    return np.concatenate([q.astype(np.float32), np.zeros(q.shape, np.float32)])
+
+
+def time_solves(torch, eq, state0, work, method, width, reps, warmup):
+    """Mean ms per solve over `reps` solves (events on the library's stream)."""
+    dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    return start.elapsed_time(stop) / reps, wall / reps
+
+
+def cpu_baseline(work, eq, budget_s):
+    """The oracle as it stands on the host cores, on a bounded sample."""
+    import oracle
+    q = wl.initial_state(work)
+    chunk = 20
+    done, t_used = 0, 0.0
+    if eq in (sw.HEAT_F64, sw.HEAT_F32):
+        run = oracle.heat_f64
+        arg = work.dt / (work.dx * work.dx)
+        cells = work.n
+    else:
+        # one Sod tile: the tiled problem is periodic with the tile's period
+        q = q[:, : work.tile]
+        run = oracle.euler_f64
+        arg = work.dt / work.dx
+        cells = work.tile
+    while t_used < budget_s and done < work.steps:
+        t0 = time.perf_counter()
+        q = run(q, chunk, arg)
+        t_used += time.perf_counter() - t0
+        done += chunk
+    return {
+        "value": cells * done / t_used,
+        "unit": "cell-updates/s",
+        "cores": oracle.threads_used(),
+        "kind": "oracle",
+        "sample": f"{cells} cells x {done} time steps of the same workload, binary64, "
+                  f"{t_used:.1f} s wall on {oracle.threads_used()} OpenMP threads",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
+    ap.add_argument("--workload", default="heat_f64_large", choices=sorted(WORKLOADS))
+    ap.add_argument("--width", type=int, default=0, help="triangle width (0: library choice)")
+    ap.add_argument("--naive-reps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the swept path here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); run with --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    work, eq = WORKLOADS[args.workload]
+    sw.load()
+    width = args.width or sw.sw_default_width(eq, work.n)
+    s = 4 if eq in (sw.EULER_F64, sw.EULER_F32) else 1
+    final_level = work.steps * s
+    phases = sw.sw_phase_count(final_level, width)
+    state0 = pack_state(eq, wl.initial_state(work))
+    updates = work.n * work.steps
+
+    log(f"[bench] workload {work.name} eq={eq} W={width} phases={phases}")
+    ms, wall_ms = time_solves(torch, eq, state0, work, "swept", width, args.steps, args.warmup)
+    log(f"[bench] swept {ms:.3f} ms/solve ({updates / ms * 1e3:.4g} cell-updates/s)")
+    naive_ms, _ = time_solves(torch, eq, state0, work, "naive", 0, args.naive_reps, 1)
+    log(f"[bench] naive {naive_ms:.3f} ms/solve ({updates / naive_ms * 1e3:.4g} cell-updates/s)")
+
+    value = updates / (ms * 1e-3)
+    naive_value = updates / (naive_ms * 1e-3)
+    launch_ms = ms / phases
+    tiles = work.n // width
+    # dominant kernel: the swept phase kernel (Diamond shape, all but 2 of the launches)
+    alg_bytes = tiles * ((width + 2) + width) * STRUCT_BYTES[eq]
+    achieved_gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
+    flops_per_launch = (HEAT_FLOPS if eq in (sw.HEAT_F64, sw.HEAT_F32) else None)
+    roofline = {
+        "bound": "hbm",
+        "achieved": achieved_gbs,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved_gbs / HBM_PEAK_GBS,
+        "traffic": None,
+        "kernel": "swept phase kernel",
+        "launch_ms": launch_ms,
+        "algorithmic_bytes_per_launch": alg_bytes,
+    }
+    if flops_per_launch:
+        ops = value * flops_per_launch
+        roofline["fp64_ops_per_s"] = ops
+        roofline["fp64_nonfma_peak"] = FP64_VECTOR_TFLOPS / 2 * 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if eq in (sw.HEAT_F64, sw.EULER_F64) else "f32",
+        "data": "synthetic",
+        "config": {"workload": work.name, "n_cells": work.n, "time_steps": work.steps,
+                   "width": width, "method": "swept", "parallelism": "single-gpu"},
+        "naive": {"value": naive_value, "ms_per_step": naive_ms,
+                  "hbm_roofline_value": HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]},
+        "swept_over_naive": value / naive_value,
+        "effective_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]),
+        "roofline": roofline,
+        "wall_ms_per_step": wall_ms,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(work, eq, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,175 @@
+/*
+ * swept.h -- C ABI of the swept-rule stencil library (MI355X / gfx950).
+ *
+ * The library advances a periodic 1D grid of n_cells cells by n_steps
+ * explicit time steps, either with the swept time-space decomposition
+ * (Magee, Walker & Niemeyer, Sec. 4.1: Up Triangle, Diamond (repeated),
+ * Down Triangle, with block edges exchanged between phases) or with the
+ * classic one-launch-per-sub-step decomposition the paper compares it with
+ * (Sec. 4.1, "Classic").  Both use the same numerical method, so for every
+ * valid input they leave bit-identical results in the state buffer.
+ *
+ * Equations (Sec. 4.2; sub-step layout of Sec. 4.3, Fig. 2b):
+ *   heat  : u_t = u_xx, first order forward in time, central in space,
+ *           r = dt / (dx * dx); one sub-step per time step.
+ *   euler : 1D Euler equations, gamma = 1.4, second-order finite volume with
+ *           a minmod limiter driven by a stored pressure ratio, predictor /
+ *           corrector in time; lambda = dt / dx; four three-point sub-steps
+ *           per time step: Pr(Q0), predictor, Pr(Q1), corrector.
+ *
+ * Precisions:
+ *   *_F64 : binary64 throughout.
+ *   *_F32 : binary32 state and flux arithmetic; the time update is
+ *           accumulated with Kahan compensation whose running compensation is
+ *           part of the state; Euler keeps the velocity / pressure /
+ *           sound-speed recovery, the pressure ratio and the limiter value in
+ *           binary64.  r and lambda are rounded to binary32 once.
+ *
+ * State layout (d_state, structure of arrays, n = n_cells, one allocation):
+ *   SW_HEAT_F64  : double u[n]
+ *   SW_HEAT_F32  : float  u[n], c[n]                  (c = Kahan compensation)
+ *   SW_EULER_F64 : double rho[n], m[n], E[n]          (m = rho*u, E = total energy)
+ *   SW_EULER_F32 : float  rho[n], m[n], E[n], c_rho[n], c_m[n], c_E[n]
+ * The buffer is device memory of the current HIP device, at least
+ * sw_state_bytes() long and 16-byte aligned.  It is read as the state at step
+ * 0 and overwritten in place with the state at step n_steps.  Before the first
+ * call of an F32 state the caller zeroes the compensations.  The state buffer
+ * alone is a complete checkpoint: solving n1 then n2 steps equals n1 + n2.
+ *
+ * Ownership: the caller owns d_state; the library never frees caller memory.
+ * Working arrays are owned and cached by the library (released by
+ * sw_release()) unless the caller passes one in sw_opts.
+ *
+ * Asynchrony: calls enqueue on `stream` (a hipStream_t; NULL = null stream)
+ * and return without waiting.  A kernel fault surfaces at the caller's next
+ * synchronisation; a launch error is reported as SW_ERR_HIP.
+ *
+ * Errors: every function returns an sw_status.  Argument checks run on the
+ * host before any HIP call, so an invalid call touches no device state.
+ * sw_last_error() returns a message for the last failure on this thread.
+ * Stability (r <= 1/2, CFL <= 1) is not checked.
+ */
+#ifndef SWEPT_H
+#define SWEPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SW_OK = 0,
+    SW_ERR_ARG = 1,         /* invalid argument (message in sw_last_error) */
+    SW_ERR_UNSUPPORTED = 2, /* no valid triangle width for this grid       */
+    SW_ERR_HIP = 3,         /* a HIP runtime call or launch failed          */
+    SW_ERR_NOMEM = 4,       /* working-array allocation failed              */
+    SW_ERR_CAPTURE = 5      /* stream is capturing and no workspace given   */
+} sw_status;
+
+typedef enum {
+    SW_HEAT_F64 = 0,
+    SW_HEAT_F32 = 1,
+    SW_EULER_F64 = 2,
+    SW_EULER_F32 = 3
+} sw_equation;
+
+typedef enum {
+    SW_METHOD_SWEPT = 0, /* Up Triangle / Diamond / Down Triangle in LDS */
+    SW_METHOD_NAIVE = 1  /* one kernel launch per sub-step (Classic)     */
+} sw_method;
+
+/* A hipStream_t passed through the ABI as an opaque pointer. */
+typedef void *sw_stream;
+
+/* Optional launch controls of swept_solve_ex / naive_solve_ex.
+ *   width           : triangle width W in cells (swept only).  0 = library
+ *                     choice.  Valid W: even, W >= 2, W divides n_cells,
+ *                     n_cells / W >= 2, W <= sw_max_width(eq).
+ *   d_workspace     : device working arrays supplied by the caller (at least
+ *                     sw_workspace_bytes() long, 256-byte aligned), or NULL
+ *                     for the library's cached arrays.  Required when the
+ *                     stream is being captured into a graph.
+ *   workspace_bytes : size of d_workspace.                                  */
+typedef struct {
+    int width;
+    int reserved0;
+    void *d_workspace;
+    size_t workspace_bytes;
+} sw_opts;
+
+/* Bytes of the state buffer for `eq` and n_cells (0 for an invalid eq). */
+size_t sw_state_bytes(int eq, int64_t n_cells);
+
+/* Bytes of working arrays a call needs: the swept method holds two copies of
+ * the per-cell working struct (heat F64 16 B, heat F32 12 B, Euler F64 56 B,
+ * Euler F32 44 B per cell); the naive method holds the second time level
+ * (heat) or the predictor state and pressure ratio (Euler).  `width` is
+ * unused by either method and may be 0.  0 for invalid arguments. */
+size_t sw_workspace_bytes(int eq, int64_t n_cells, int width, int method);
+
+/* Largest triangle width the swept kernels accept for `eq` (set by the LDS
+ * a tile needs: (W + 2) cells of working struct plus scratch, within the
+ * 160 KiB of LDS of one gfx950 compute unit).  0 for an invalid eq. */
+int sw_max_width(int eq);
+
+/* The width swept_solve picks when none is given: the largest even divisor
+ * of n_cells not above the preferred width for `eq` with n_cells / W >= 2.
+ * 0 when there is none. */
+int sw_default_width(int eq, int64_t n_cells);
+
+/* Swept-rule solve (Sec. 4.1).  Advances d_state by n_steps time steps.
+ * dt, dx: finite and > 0.  n_steps >= 0 (0 is a no-op).  n_cells >= 4. */
+int swept_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
+                void *d_state, sw_stream stream);
+
+/* Classic decomposition: one kernel launch per sub-step (Sec. 4.1, Fig. 2b).
+ * Same arguments and result as swept_solve.  n_cells >= 3. */
+int naive_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
+                void *d_state, sw_stream stream);
+
+/* As swept_solve / naive_solve with launch controls (opts may be NULL). */
+int swept_solve_ex(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
+                   void *d_state, sw_stream stream, const sw_opts *opts);
+int naive_solve_ex(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
+                   void *d_state, sw_stream stream, const sw_opts *opts);
+
+/* ---- schedule queries (host only, no HIP call) ------------------------
+ * The swept schedule for a final sub-step level F (F = n_steps for heat,
+ * 4 * n_steps for Euler) and width W = 2H has
+ *   K = 0 if F == 0, else ceil((F - 1) / H) + 1
+ * phases.  Phase k (1-based) tiles the grid from cell offset
+ * ((k - 1) % 2) * H in tiles of W cells; it lifts cell o of a tile
+ * (o in [0, W), p(o) = min(o + 1, W - o)) from sub-step level
+ * min(F, max(0, (k-1)H + 1 - p(o))) to min(F, (k-1)H + p(o)).  Phase 1 is the
+ * Up Triangle, phase K the Down Triangle, the others Diamonds (the last ones
+ * cut flat at F when F is not a multiple of H).                           */
+
+/* Number of phases K; -1 for invalid arguments. */
+int64_t sw_phase_count(int64_t final_level, int width);
+
+/* For phase k: the cell offset of its tiling and its first and last
+ * sub-step level (first > last when the phase computes nothing).
+ * SW_ERR_ARG for invalid arguments. */
+int sw_phase_info(int64_t k, int64_t final_level, int width, int64_t *offset,
+                  int64_t *first_level, int64_t *last_level);
+
+/* Active cells of a tile of phase k at sub-step `level`: [*lo, *hi) in tile
+ * coordinates (empty when *lo >= *hi).  SW_ERR_ARG for invalid arguments. */
+int sw_phase_interval(int64_t k, int64_t final_level, int width, int64_t level, int *lo,
+                      int *hi);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next library call on the same thread. */
+const char *sw_last_error(void);
+
+/* Free the library's cached working arrays on every device (synchronises
+ * each device that holds one). */
+void sw_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWEPT_H */

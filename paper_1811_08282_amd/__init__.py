@@ -1,0 +1,203 @@
+"""Swept-rule stencil library for MI355X (gfx950) -- Python binding.
+
+Thin ctypes marshalling over the C ABI in ``include/swept.h``; every step of
+the computation runs in the HIP kernels of ``libswept.so``.  The functions
+``swept_solve``, ``naive_solve`` (and the ``_ex`` forms) take raw device
+pointers and a HIP stream handle exactly like the C functions; :func:`solve`
+is a convenience wrapper for ``torch`` device tensors (torch provides device
+memory and streams only).
+
+The library must be built first (``python -m paper_1811_08282_amd.build``);
+loading fails loudly when it is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswept.so")
+
+# equation x precision ids (sw_equation)
+HEAT_F64, HEAT_F32, EULER_F64, EULER_F32 = 0, 1, 2, 3
+EQUATIONS = {"heat_f64": HEAT_F64, "heat_f32": HEAT_F32,
+             "euler_f64": EULER_F64, "euler_f32": EULER_F32}
+# methods (sw_method)
+METHOD_SWEPT, METHOD_NAIVE = 0, 1
+# status codes (sw_status)
+SW_OK, SW_ERR_ARG, SW_ERR_UNSUPPORTED, SW_ERR_HIP, SW_ERR_NOMEM, SW_ERR_CAPTURE = range(6)
+STATUS_NAMES = {0: "SW_OK", 1: "SW_ERR_ARG", 2: "SW_ERR_UNSUPPORTED", 3: "SW_ERR_HIP",
+                4: "SW_ERR_NOMEM", 5: "SW_ERR_CAPTURE"}
+
+
+class SweptError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class sw_opts(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("reserved0", ctypes.c_int),
+                ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load ``libswept.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1811_08282_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, i32, d, vp, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+    solve_args = [i32, i64, i64, d, d, vp, vp]
+    for name in ("swept_solve", "naive_solve"):
+        getattr(lib, name).argtypes = solve_args
+        getattr(lib, name).restype = i32
+    for name in ("swept_solve_ex", "naive_solve_ex"):
+        getattr(lib, name).argtypes = solve_args + [ctypes.POINTER(sw_opts)]
+        getattr(lib, name).restype = i32
+    lib.sw_state_bytes.argtypes = [i32, i64]
+    lib.sw_state_bytes.restype = sz
+    lib.sw_workspace_bytes.argtypes = [i32, i64, i32, i32]
+    lib.sw_workspace_bytes.restype = sz
+    lib.sw_max_width.argtypes = [i32]
+    lib.sw_max_width.restype = i32
+    lib.sw_default_width.argtypes = [i32, i64]
+    lib.sw_default_width.restype = i32
+    lib.sw_phase_count.argtypes = [i64, i32]
+    lib.sw_phase_count.restype = i64
+    lib.sw_phase_info.argtypes = [i64, i64, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                  ctypes.POINTER(i64)]
+    lib.sw_phase_info.restype = i32
+    lib.sw_phase_interval.argtypes = [i64, i64, i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.sw_phase_interval.restype = i32
+    lib.sw_last_error.argtypes = []
+    lib.sw_last_error.restype = ctypes.c_char_p
+    lib.sw_release.argtypes = []
+    lib.sw_release.restype = None
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().sw_last_error().decode()
+
+
+def _opts(width: int = 0, workspace: int | None = None, workspace_bytes: int = 0):
+    o = sw_opts()
+    o.width = int(width)
+    o.reserved0 = 0
+    o.d_workspace = workspace
+    o.workspace_bytes = int(workspace_bytes)
+    return o
+
+
+# ---- raw C-ABI mirrors (device pointers as ints) ---------------------------
+
+def swept_solve(eq, n_cells, n_steps, dt, dx, d_state, stream=None) -> int:
+    return load().swept_solve(eq, n_cells, n_steps, dt, dx, d_state, stream)
+
+
+def naive_solve(eq, n_cells, n_steps, dt, dx, d_state, stream=None) -> int:
+    return load().naive_solve(eq, n_cells, n_steps, dt, dx, d_state, stream)
+
+
+def swept_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream=None, width=0,
+                   workspace=None, workspace_bytes=0) -> int:
+    o = _opts(width, workspace, workspace_bytes)
+    return load().swept_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream, ctypes.byref(o))
+
+
+def naive_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream=None, workspace=None,
+                   workspace_bytes=0) -> int:
+    o = _opts(0, workspace, workspace_bytes)
+    return load().naive_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream, ctypes.byref(o))
+
+
+def sw_state_bytes(eq, n_cells) -> int:
+    return load().sw_state_bytes(eq, n_cells)
+
+
+def sw_workspace_bytes(eq, n_cells, width=0, method=METHOD_SWEPT) -> int:
+    return load().sw_workspace_bytes(eq, n_cells, width, method)
+
+
+def sw_max_width(eq) -> int:
+    return load().sw_max_width(eq)
+
+
+def sw_default_width(eq, n_cells) -> int:
+    return load().sw_default_width(eq, n_cells)
+
+
+def sw_phase_count(final_level, width) -> int:
+    return load().sw_phase_count(final_level, width)
+
+
+def sw_phase_info(k, final_level, width):
+    off, first, last = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    rc = load().sw_phase_info(k, final_level, width, ctypes.byref(off), ctypes.byref(first),
+                              ctypes.byref(last))
+    if rc:
+        raise SweptError(rc, last_error())
+    return off.value, first.value, last.value
+
+
+def sw_phase_interval(k, final_level, width, level):
+    lo, hi = ctypes.c_int(), ctypes.c_int()
+    rc = load().sw_phase_interval(k, final_level, width, level, ctypes.byref(lo), ctypes.byref(hi))
+    if rc:
+        raise SweptError(rc, last_error())
+    return lo.value, hi.value
+
+
+def sw_release() -> None:
+    load().sw_release()
+
+
+# ---- torch convenience -----------------------------------------------------
+
+def substeps(eq: int) -> int:
+    return 4 if eq in (EULER_F64, EULER_F32) else 1
+
+
+def state_dtype(eq: int):
+    import torch
+    return torch.float64 if eq in (HEAT_F64, EULER_F64) else torch.float32
+
+
+def state_rows(eq: int) -> int:
+    """Arrays of n_cells in the state buffer (see include/swept.h)."""
+    return {HEAT_F64: 1, HEAT_F32: 2, EULER_F64: 3, EULER_F32: 6}[eq]
+
+
+def solve(eq: int, state, n_steps: int, dt: float, dx: float, method: str = "swept",
+          width: int = 0, workspace=None, stream=None) -> None:
+    """Advance a torch device tensor of shape (rows, n_cells) in place.
+
+    ``rows`` is :func:`state_rows`; the dtype is float64 for *_F64 and float32
+    for *_F32.  Runs on ``stream`` (default: torch's current stream).
+    """
+    import torch
+    if not state.is_cuda or not state.is_contiguous():
+        raise ValueError("state must be a contiguous device tensor")
+    if state.dtype != state_dtype(eq) or state.dim() != 2 or state.shape[0] != state_rows(eq):
+        raise ValueError(f"state must have shape ({state_rows(eq)}, n) and dtype {state_dtype(eq)}")
+    n = state.shape[1]
+    s = stream if stream is not None else torch.cuda.current_stream()
+    handle = s.cuda_stream
+    ws_ptr = workspace.data_ptr() if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    if method == "swept":
+        rc = swept_solve_ex(eq, n, n_steps, dt, dx, state.data_ptr(), handle, width, ws_ptr, ws_bytes)
+    elif method == "naive":
+        rc = naive_solve_ex(eq, n, n_steps, dt, dx, state.data_ptr(), handle, ws_ptr, ws_bytes)
+    else:
+        raise ValueError("method must be 'swept' or 'naive'")
+    if rc != SW_OK:
+        raise SweptError(rc, last_error())

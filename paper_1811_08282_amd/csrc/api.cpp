@@ -1,0 +1,487 @@
+// api.cpp -- host side of the C ABI: argument checks, the swept planner,
+// working-array management and the launch sequences of both methods.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "../../include/swept.h"
+#include "geom.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok()
+{
+    g_err.clear();
+    return SW_OK;
+}
+
+bool valid_eq(int eq) { return eq >= SW_HEAT_F64 && eq <= SW_EULER_F32; }
+bool is_euler(int eq) { return eq == SW_EULER_F64 || eq == SW_EULER_F32; }
+int substeps(int eq) { return is_euler(eq) ? 4 : 1; }
+
+constexpr int64_t kMaxCells = (int64_t)1 << 40;
+constexpr int64_t kMaxWidth = 8192;
+
+int lds_per_cell(int eq)
+{
+    switch (eq) {
+    case SW_HEAT_F64: return sw::kLdsPerCellHeatF64;
+    case SW_HEAT_F32: return sw::kLdsPerCellHeatF32;
+    case SW_EULER_F64: return sw::kLdsPerCellEulerF64;
+    default: return sw::kLdsPerCellEulerF32;
+    }
+}
+
+int struct_bytes(int eq)
+{
+    switch (eq) {
+    case SW_HEAT_F64: return sw::kStructBytesHeatF64;
+    case SW_HEAT_F32: return sw::kStructBytesHeatF32;
+    case SW_EULER_F64: return sw::kStructBytesEulerF64;
+    default: return sw::kStructBytesEulerF32;
+    }
+}
+
+int preferred_width(int eq) { return is_euler(eq) ? 256 : 1024; }
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int max_width(int eq)
+{
+    int64_t w = sw::kLdsBytes / lds_per_cell(eq) - 2;
+    if (w > kMaxWidth)
+        w = kMaxWidth;
+    return (int)(w & ~(int64_t)1);
+}
+
+bool width_ok(int eq, int64_t n, int64_t w)
+{
+    return w >= 2 && (w % 2) == 0 && w <= max_width(eq) && (n % w) == 0 && n / w >= 2;
+}
+
+int default_width(int eq, int64_t n)
+{
+    for (int64_t w = preferred_width(eq); w >= 2; w -= 2)
+        if (width_ok(eq, n, w))
+            return (int)w;
+    return 0;
+}
+
+size_t state_bytes(int eq, int64_t n)
+{
+    switch (eq) {
+    case SW_HEAT_F64: return (size_t)n * 8;
+    case SW_HEAT_F32: return (size_t)n * 8;
+    case SW_EULER_F64: return (size_t)n * 24;
+    default: return (size_t)n * 24;
+    }
+}
+
+// one copy of the swept working arrays, 256-byte rounded
+size_t swept_copy_bytes(int eq, int64_t n) { return round_up((size_t)n * struct_bytes(eq), 256); }
+
+size_t naive_ws_bytes(int eq, int64_t n)
+{
+    switch (eq) {
+    case SW_HEAT_F64: return round_up((size_t)n * 8, 256);
+    case SW_HEAT_F32: return round_up((size_t)n * 4, 256);
+    case SW_EULER_F64: return round_up((size_t)n * 24, 256) + round_up((size_t)n * 8, 256);
+    default: return round_up((size_t)n * 12, 256) + round_up((size_t)n * 8, 256);
+    }
+}
+
+// ---- argument checks (no HIP call) -----------------------------------------
+
+int check_common(int eq, int64_t n, int64_t steps, double dt, double dx, const void *state,
+                 int64_t min_cells)
+{
+    if (!valid_eq(eq))
+        return fail(SW_ERR_ARG, "invalid equation id %d", eq);
+    if (n < min_cells || n > kMaxCells)
+        return fail(SW_ERR_ARG, "n_cells %lld out of range [%lld, 2^40]", (long long)n,
+                    (long long)min_cells);
+    if (steps < 0 || steps > INT64_MAX / 8)
+        return fail(SW_ERR_ARG, "n_steps %lld out of range", (long long)steps);
+    if (!(dt > 0.0) || !isfinite(dt))
+        return fail(SW_ERR_ARG, "dt must be finite and > 0");
+    if (!(dx > 0.0) || !isfinite(dx))
+        return fail(SW_ERR_ARG, "dx must be finite and > 0");
+    if (!state)
+        return fail(SW_ERR_ARG, "d_state is NULL");
+    if (((uintptr_t)state & 15) != 0)
+        return fail(SW_ERR_ARG, "d_state must be 16-byte aligned");
+    return SW_OK;
+}
+
+// ---- device-side checks and working arrays ------------------------------------
+
+int check_device_pointer(const void *p, int *dev_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_HIP, "hipGetDevice failed");
+    }
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_ARG, "d_state is not a HIP device pointer");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(SW_ERR_ARG, "d_state is not device memory");
+    if (attr.device != dev)
+        return fail(SW_ERR_ARG, "d_state lives on device %d, current device is %d", attr.device,
+                    dev);
+    *dev_out = dev;
+    return SW_OK;
+}
+
+struct CachedWs {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+std::mutex g_ws_mutex;
+std::map<std::pair<int, void *>, CachedWs> g_ws;  // (device, stream) -> arrays
+
+// Working arrays for a call: the caller's (opts) or the cache of this
+// (device, stream).  Growing the cache synchronises the device first, so no
+// earlier launch still uses the old arrays when they are freed.
+int get_workspace(int dev, hipStream_t stream, size_t need, const sw_opts *o, void **out)
+{
+    if (o && o->d_workspace) {
+        if (o->workspace_bytes < need)
+            return fail(SW_ERR_ARG, "workspace of %zu bytes is smaller than the %zu needed",
+                        o->workspace_bytes, need);
+        if (((uintptr_t)o->d_workspace & 255) != 0)
+            return fail(SW_ERR_ARG, "workspace must be 256-byte aligned");
+        *out = o->d_workspace;
+        return SW_OK;
+    }
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    CachedWs &c = g_ws[std::make_pair(dev, (void *)stream)];
+    if (c.bytes >= need) {
+        *out = c.ptr;
+        return SW_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_HIP, "hipStreamIsCapturing failed");
+    }
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(SW_ERR_CAPTURE,
+                    "stream is capturing and the cached working arrays are too small; pass a "
+                    "workspace in sw_opts");
+    if (c.ptr) {
+        if (hipDeviceSynchronize() != hipSuccess || hipFree(c.ptr) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SW_ERR_HIP, "releasing old working arrays failed");
+        }
+        c.ptr = nullptr;
+        c.bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_NOMEM, "hipMalloc of %zu bytes for working arrays failed", need);
+    }
+    c.ptr = p;
+    c.bytes = need;
+    *out = p;
+    return SW_OK;
+}
+
+int launched(hipError_t e, const char *what)
+{
+    if (e != hipSuccess)
+        return fail(SW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return SW_OK;
+}
+
+// ---- the two methods ---------------------------------------------------------
+
+int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *state,
+              hipStream_t s, int w, void *ws)
+{
+    const int64_t final_level = steps * substeps(eq);
+    const int64_t half = w / 2;
+    const int64_t phases = sw::phase_count(final_level, half);
+    const size_t copy = swept_copy_bytes(eq, n);
+    char *ws_a = (char *)ws;
+    char *ws_b = ws_a + copy;
+    const double r64 = dt / (dx * dx);
+    const double lam64 = dt / dx;
+    for (int64_t k = 1; k <= phases; ++k) {
+        const sw::PhaseRange pr = sw::phase_range(k, final_level, half);
+        sw::PhaseLaunch p;
+        p.n = n;
+        p.w = w;
+        p.offset = pr.offset;
+        p.base = pr.base;
+        p.j_first = pr.j_first;
+        p.j_last = pr.j_last;
+        p.first = (k == 1);
+        // A single phase (heat, one step) may not write the caller's state:
+        // its tiles read their halos from that same state.  It writes the
+        // working array, and level 1 (slot 1) is copied back below.
+        p.last = (k == phases) && phases > 1;
+        char *in = (k % 2 == 0) ? ws_a : ws_b;
+        char *out = (k % 2 == 1) ? ws_a : ws_b;
+        hipError_t e = hipSuccess;
+        switch (eq) {
+        case SW_HEAT_F64:
+            e = sw::heat_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out,
+                                         r64, s);
+            break;
+        case SW_HEAT_F32:
+            e = sw::heat_f32_swept_phase(p, (float *)state, (const float *)in, (float *)out,
+                                         (float)r64, s);
+            break;
+        case SW_EULER_F64:
+            e = sw::euler_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out,
+                                          lam64, s);
+            break;
+        default:
+            e = sw::euler_f32_swept_phase(p, (float *)state, in, out, (float)lam64, s);
+            break;
+        }
+        if (e != hipSuccess)
+            return launched(e, "swept phase launch");
+    }
+    if (phases == 1) {
+        // only heat reaches here (one step: final level 1); copy slot 1 (and
+        // the binary32 compensation) from working array A to the state
+        hipError_t e = hipSuccess;
+        if (eq == SW_HEAT_F64) {
+            e = hipMemcpyAsync(state, ws_a + (size_t)n * 8, (size_t)n * 8, hipMemcpyDeviceToDevice,
+                               s);
+        } else if (eq == SW_HEAT_F32) {
+            e = hipMemcpyAsync(state, ws_a + (size_t)n * 4, (size_t)n * 8, hipMemcpyDeviceToDevice,
+                               s);
+        } else {
+            return fail(SW_ERR_HIP, "internal: single-phase schedule for a four-sub-step scheme");
+        }
+        if (e != hipSuccess)
+            return launched(e, "swept single-phase copy");
+    }
+    return SW_OK;
+}
+
+int run_naive(int eq, int64_t n, int64_t steps, double dt, double dx, void *state,
+              hipStream_t s, void *ws)
+{
+    const double r64 = dt / (dx * dx);
+    const double lam64 = dt / dx;
+    hipError_t e = hipSuccess;
+    if (eq == SW_HEAT_F64 || eq == SW_HEAT_F32) {
+        const size_t elem = (eq == SW_HEAT_F64) ? 8 : 4;
+        char *cur = (char *)state, *nxt = (char *)ws;
+        for (int64_t t = 0; t < steps && e == hipSuccess; ++t) {
+            if (eq == SW_HEAT_F64)
+                e = sw::heat_f64_naive_step((const double *)cur, (double *)nxt, n, r64, s);
+            else
+                e = sw::heat_f32_naive_step((const float *)cur, (float *)nxt,
+                                            (float *)state + n, n, (float)r64, s);
+            std::swap(cur, nxt);
+        }
+        if (e == hipSuccess && cur != (char *)state)
+            e = hipMemcpyAsync(state, cur, (size_t)n * elem, hipMemcpyDeviceToDevice, s);
+        return launched(e, "naive heat launch");
+    }
+    if (eq == SW_EULER_F64) {
+        double *q0 = (double *)state;
+        double *q1 = (double *)ws;
+        double *pr = (double *)((char *)ws + round_up((size_t)n * 24, 256));
+        for (int64_t t = 0; t < steps && e == hipSuccess; ++t)
+            for (int sub = 0; sub < 4 && e == hipSuccess; ++sub)
+                e = sw::euler_f64_naive_substep(sub, q0, q1, pr, n, lam64, s);
+        return launched(e, "naive euler launch");
+    }
+    float *q0c = (float *)state;
+    float *q1 = (float *)ws;
+    double *pr = (double *)((char *)ws + round_up((size_t)n * 12, 256));
+    for (int64_t t = 0; t < steps && e == hipSuccess; ++t)
+        for (int sub = 0; sub < 4 && e == hipSuccess; ++sub)
+            e = sw::euler_f32_naive_substep(sub, q0c, q1, pr, n, (float)lam64, s);
+    return launched(e, "naive euler launch");
+}
+
+int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, void *state,
+          sw_stream stream, const sw_opts *o)
+{
+    int rc = check_common(eq, n, steps, dt, dx, state, method == SW_METHOD_SWEPT ? 4 : 3);
+    if (rc)
+        return rc;
+    int w = 0;
+    if (method == SW_METHOD_SWEPT) {
+        if (o && o->width) {
+            if (!width_ok(eq, n, o->width))
+                return fail(SW_ERR_ARG,
+                            "width %d invalid for n_cells %lld (even, >= 2, divides n_cells, "
+                            "n_cells/width >= 2, <= %d)",
+                            o->width, (long long)n, max_width(eq));
+            w = o->width;
+        } else {
+            w = default_width(eq, n);
+            if (!w)
+                return fail(SW_ERR_UNSUPPORTED, "no valid triangle width for n_cells %lld",
+                            (long long)n);
+        }
+    }
+    if (o && o->d_workspace && ((uintptr_t)o->d_workspace & 255) != 0)
+        return fail(SW_ERR_ARG, "workspace must be 256-byte aligned");
+    if (steps == 0)
+        return ok();
+    int dev = 0;
+    rc = check_device_pointer(state, &dev);
+    if (rc)
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t need = (method == SW_METHOD_SWEPT) ? 2 * swept_copy_bytes(eq, n)
+                                                    : naive_ws_bytes(eq, n);
+    void *ws = nullptr;
+    rc = get_workspace(dev, s, need, o, &ws);
+    if (rc)
+        return rc;
+    rc = (method == SW_METHOD_SWEPT) ? run_swept(eq, n, steps, dt, dx, state, s, w, ws)
+                                     : run_naive(eq, n, steps, dt, dx, state, s, ws);
+    return rc ? rc : ok();
+}
+
+} // namespace
+
+extern "C" {
+
+size_t sw_state_bytes(int eq, int64_t n_cells)
+{
+    if (!valid_eq(eq) || n_cells <= 0 || n_cells > kMaxCells)
+        return 0;
+    return state_bytes(eq, n_cells);
+}
+
+size_t sw_workspace_bytes(int eq, int64_t n_cells, int width, int method)
+{
+    (void)width;
+    if (!valid_eq(eq) || n_cells <= 0 || n_cells > kMaxCells)
+        return 0;
+    if (method == SW_METHOD_SWEPT)
+        return 2 * swept_copy_bytes(eq, n_cells);
+    if (method == SW_METHOD_NAIVE)
+        return naive_ws_bytes(eq, n_cells);
+    return 0;
+}
+
+int sw_max_width(int eq) { return valid_eq(eq) ? max_width(eq) : 0; }
+
+int sw_default_width(int eq, int64_t n_cells)
+{
+    if (!valid_eq(eq) || n_cells < 4 || n_cells > kMaxCells)
+        return 0;
+    return default_width(eq, n_cells);
+}
+
+int swept_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx, void *d_state,
+                sw_stream stream)
+{
+    return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, nullptr);
+}
+
+int naive_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx, void *d_state,
+                sw_stream stream)
+{
+    return solve(SW_METHOD_NAIVE, eq, n_cells, n_steps, dt, dx, d_state, stream, nullptr);
+}
+
+int swept_solve_ex(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
+                   void *d_state, sw_stream stream, const sw_opts *opts)
+{
+    return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, opts);
+}
+
+int naive_solve_ex(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
+                   void *d_state, sw_stream stream, const sw_opts *opts)
+{
+    return solve(SW_METHOD_NAIVE, eq, n_cells, n_steps, dt, dx, d_state, stream, opts);
+}
+
+int64_t sw_phase_count(int64_t final_level, int width)
+{
+    if (final_level < 0 || width < 2 || (width & 1))
+        return -1;
+    return sw::phase_count(final_level, width / 2);
+}
+
+int sw_phase_info(int64_t k, int64_t final_level, int width, int64_t *offset,
+                  int64_t *first_level, int64_t *last_level)
+{
+    const int64_t phases = sw_phase_count(final_level, width);
+    if (phases < 0 || k < 1 || k > phases || !offset || !first_level || !last_level)
+        return fail(SW_ERR_ARG, "invalid phase query");
+    const sw::PhaseRange p = sw::phase_range(k, final_level, width / 2);
+    *offset = p.offset;
+    *first_level = p.base + p.j_first;
+    *last_level = p.base + p.j_last;
+    return ok();
+}
+
+int sw_phase_interval(int64_t k, int64_t final_level, int width, int64_t level, int *lo, int *hi)
+{
+    const int64_t phases = sw_phase_count(final_level, width);
+    if (phases < 0 || k < 1 || k > phases || !lo || !hi)
+        return fail(SW_ERR_ARG, "invalid phase query");
+    const sw::PhaseRange p = sw::phase_range(k, final_level, width / 2);
+    const int64_t j = level - p.base;
+    if (j < p.j_first || j > p.j_last) {
+        *lo = 0;
+        *hi = 0;
+        return ok();
+    }
+    const int a = sw::window_margin((int)j);
+    *lo = a;
+    *hi = width - a;
+    return ok();
+}
+
+const char *sw_last_error(void) { return g_err.c_str(); }
+
+void sw_release(void)
+{
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_ws) {
+        if (!kv.second.ptr)
+            continue;
+        (void)hipSetDevice(kv.first.first);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(kv.second.ptr);
+    }
+    g_ws.clear();
+    (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+}
+
+} // extern "C"

@@ -1,0 +1,63 @@
+// kernels.h -- internal launch interface between the host planner (api.cpp)
+// and the HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sw {
+
+constexpr int kLdsBytes = 160 * 1024;  // LDS of one gfx950 compute unit
+
+// Per-cell bytes of the swept working struct held in HBM (two copies of the
+// working arrays are used, ping-ponged between phases).
+constexpr int kStructBytesHeatF64 = 16;   // u at even / odd levels
+constexpr int kStructBytesHeatF32 = 12;   // u even / odd, Kahan c
+constexpr int kStructBytesEulerF64 = 56;  // Q0[3], Q1[3], Pr
+constexpr int kStructBytesEulerF32 = 44;  // Q0[3], c[3], Q1[3] (f32), Pr (f64)
+
+// LDS bytes per tile cell of each swept kernel (struct + scratch).
+constexpr int kLdsPerCellHeatF64 = 16;
+constexpr int kLdsPerCellHeatF32 = 12;
+constexpr int kLdsPerCellEulerF64 = 80;  // struct 56 + face flux / pressure 24
+constexpr int kLdsPerCellEulerF32 = 56;  // struct 44 + face flux / pressure 12
+
+// Description of one swept phase launch.
+struct PhaseLaunch {
+    int64_t n;        // cells
+    int w;            // tile width
+    int64_t offset;   // first cell of tile 0 (0 or w/2)
+    int64_t base;     // (k - 1) * w/2
+    int j_first, j_last;
+    bool first;       // reads the caller's state (level 0 of this call)
+    bool last;        // writes the caller's state (final level)
+};
+
+// Heat, binary64.  state: u[n]; ws_in / ws_out: working arrays of 2n doubles.
+hipError_t heat_f64_swept_phase(const PhaseLaunch &p, double *state, const double *ws_in,
+                                double *ws_out, double r, hipStream_t s);
+hipError_t heat_f64_naive_step(const double *u, double *v, int64_t n, double r, hipStream_t s);
+
+// Heat, binary32 + Kahan.  state: u[n], c[n]; ws: 3n floats (u even, u odd, c).
+hipError_t heat_f32_swept_phase(const PhaseLaunch &p, float *state, const float *ws_in,
+                                float *ws_out, float r, hipStream_t s);
+hipError_t heat_f32_naive_step(const float *u, float *v, float *c, int64_t n, float r,
+                               hipStream_t s);
+
+// Euler, binary64.  state: rho, m, E [n each]; ws: 7n doubles (Q0[3], Q1[3], Pr).
+hipError_t euler_f64_swept_phase(const PhaseLaunch &p, double *state, const double *ws_in,
+                                 double *ws_out, double lam, hipStream_t s);
+// One classic sub-step of type t = 0..3 (Pr(Q0), predictor, Pr(Q1), corrector).
+// q0: caller state (3n), q1: predictor state (3n), pr: pressure ratio (n).
+hipError_t euler_f64_naive_substep(int t, double *q0, double *q1, double *pr, int64_t n,
+                                   double lam, hipStream_t s);
+
+// Euler, binary32 + Kahan + binary64 islands.  state: rho, m, E, c_rho, c_m,
+// c_E [n floats each]; ws: 9n floats (Q0[3], c[3], Q1[3]) + n doubles (Pr).
+hipError_t euler_f32_swept_phase(const PhaseLaunch &p, float *state, const void *ws_in,
+                                 void *ws_out, float lam, hipStream_t s);
+hipError_t euler_f32_naive_substep(int t, float *q0c, float *q1, double *pr, int64_t n,
+                                   float lam, hipStream_t s);
+
+} // namespace sw

@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/swept.h, sizes its buffers as documented, and rejects
+invalid arguments on the host before any HIP call."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_1811_08282_amd as sw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swept.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_library_exports_every_declared_function():
+    lib = sw.load()
+    names = _declared_functions()
+    assert "swept_solve" in names and "naive_solve" in names and len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_state_and_workspace_sizes():
+    n = 1 << 10
+    assert sw.sw_state_bytes(sw.HEAT_F64, n) == 8 * n
+    assert sw.sw_state_bytes(sw.HEAT_F32, n) == 8 * n
+    assert sw.sw_state_bytes(sw.EULER_F64, n) == 24 * n
+    assert sw.sw_state_bytes(sw.EULER_F32, n) == 24 * n
+    assert sw.sw_state_bytes(7, n) == 0
+    for eq, per_cell in ((sw.HEAT_F64, 16), (sw.HEAT_F32, 12), (sw.EULER_F64, 56), (sw.EULER_F32, 44)):
+        assert sw.sw_workspace_bytes(eq, n, 0, sw.METHOD_SWEPT) == 2 * per_cell * n
+    assert sw.sw_workspace_bytes(sw.HEAT_F64, n, 0, sw.METHOD_NAIVE) == 8 * n
+    assert sw.sw_workspace_bytes(sw.EULER_F64, n, 0, sw.METHOD_NAIVE) == 32 * n
+    assert sw.sw_workspace_bytes(sw.EULER_F64, n, 0, 9) == 0
+
+
+def test_width_limits():
+    for eq, per_cell in ((sw.HEAT_F64, 16), (sw.HEAT_F32, 12), (sw.EULER_F64, 80), (sw.EULER_F32, 56)):
+        wmax = sw.sw_max_width(eq)
+        assert wmax % 2 == 0 and (wmax + 2) * per_cell <= 160 * 1024 and wmax <= 8192
+    assert sw.sw_default_width(sw.HEAT_F64, 1 << 22) == 1024
+    assert sw.sw_default_width(sw.EULER_F64, 1 << 22) == 256
+    assert sw.sw_default_width(sw.HEAT_F64, 1000) == 500  # largest even divisor with n/W >= 2
+    assert sw.sw_default_width(sw.HEAT_F64, 1001) == 0    # odd: no even divisor
+    assert sw.sw_default_width(sw.HEAT_F64, 6) == 2
+
+
+FAKE = 0x1000  # never dereferenced: every case below fails or returns before any HIP call
+
+
+@pytest.mark.parametrize("fn", ["swept", "naive"])
+@pytest.mark.parametrize("args,code", [
+    ((9, 64, 1, 0.1, 1.0, FAKE), sw.SW_ERR_ARG),               # bad equation id
+    ((sw.HEAT_F64, 2, 1, 0.1, 1.0, FAKE), sw.SW_ERR_ARG),      # too few cells
+    ((sw.HEAT_F64, 64, -1, 0.1, 1.0, FAKE), sw.SW_ERR_ARG),    # negative steps
+    ((sw.HEAT_F64, 64, 1, 0.0, 1.0, FAKE), sw.SW_ERR_ARG),     # dt <= 0
+    ((sw.HEAT_F64, 64, 1, math.nan, 1.0, FAKE), sw.SW_ERR_ARG),
+    ((sw.HEAT_F64, 64, 1, 0.1, math.inf, FAKE), sw.SW_ERR_ARG),
+    ((sw.HEAT_F64, 64, 1, 0.1, -1.0, FAKE), sw.SW_ERR_ARG),
+    ((sw.HEAT_F64, 64, 1, 0.1, 1.0, None), sw.SW_ERR_ARG),     # null state
+    ((sw.HEAT_F64, 64, 1, 0.1, 1.0, FAKE + 8), sw.SW_ERR_ARG),  # misaligned
+    ((sw.EULER_F32, 64, 0, 0.1, 1.0, FAKE), sw.SW_OK),        # zero steps: no-op
+])
+def test_host_validation(fn, args, code):
+    f = sw.swept_solve if fn == "swept" else sw.naive_solve
+    assert f(*args, None) == code
+    if code != sw.SW_OK:
+        assert sw.last_error()
+
+
+@pytest.mark.parametrize("width", [3, 0 - 2, 6, 1024, 100000])
+def test_invalid_width_rejected_on_host(width):
+    # n = 1024: 6 does not divide it, 1024 leaves one tile, 100000 is too wide
+    rc = sw.swept_solve_ex(sw.HEAT_F64, 1024, 5, 0.25, 1.0, FAKE, None, width=width)
+    assert rc == sw.SW_ERR_ARG, sw.last_error()
+
+
+def test_no_valid_width_is_unsupported():
+    assert sw.swept_solve(sw.HEAT_F64, 1001, 5, 0.25, 1.0, FAKE, None) == sw.SW_ERR_UNSUPPORTED
+    # the classic method accepts any n >= 3
+    assert sw.naive_solve(sw.HEAT_F64, 1001, 0, 0.25, 1.0, FAKE, None) == sw.SW_OK
+
+
+def test_misaligned_workspace_rejected():
+    rc = sw.swept_solve_ex(sw.HEAT_F64, 1024, 5, 0.25, 1.0, FAKE, None, width=64,
+                           workspace=FAKE + 16, workspace_bytes=1 << 20)
+    assert rc == sw.SW_ERR_ARG
+
+
+def test_python_binding_names_match_c_abi():
+    for name in ("swept_solve", "naive_solve", "swept_solve_ex", "naive_solve_ex",
+                 "sw_state_bytes", "sw_workspace_bytes", "sw_max_width", "sw_default_width",
+                 "sw_phase_count", "sw_phase_info", "sw_phase_interval", "sw_release"):
+        assert callable(getattr(sw, name))
+    assert ctypes.sizeof(sw.sw_opts) == 24
