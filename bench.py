@@ -126,6 +126,9 @@ def main() -> int:
     ap.add_argument("--naive-reps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-naive", action="store_true", help="skip the classic-path timing")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -139,6 +142,15 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(args.steps, 1)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}))
+        return 0
     work, eq = WORKLOADS[args.workload]
     sw.load()
     width = args.width or sw.sw_default_width(eq, work.n)
@@ -151,11 +163,13 @@ def main() -> int:
     log(f"[bench] workload {work.name} eq={eq} W={width} phases={phases}")
     ms, wall_ms = time_solves(torch, eq, state0, work, "swept", width, args.steps, args.warmup)
     log(f"[bench] swept {ms:.3f} ms/solve ({updates / ms * 1e3:.4g} cell-updates/s)")
-    naive_ms, _ = time_solves(torch, eq, state0, work, "naive", 0, args.naive_reps, 1)
-    log(f"[bench] naive {naive_ms:.3f} ms/solve ({updates / naive_ms * 1e3:.4g} cell-updates/s)")
+    naive_ms = float("nan")
+    if not args.no_naive:
+        naive_ms, _ = time_solves(torch, eq, state0, work, "naive", 0, args.naive_reps, 1)
+        log(f"[bench] naive {naive_ms:.3f} ms/solve ({updates / naive_ms * 1e3:.4g} cell-updates/s)")
 
     value = updates / (ms * 1e-3)
-    naive_value = updates / (naive_ms * 1e-3)
+    naive_value = updates / (naive_ms * 1e-3) if naive_ms == naive_ms else None
     launch_ms = ms / phases
     tiles = work.n // width
     # dominant kernel: the swept phase kernel (Diamond shape, all but 2 of the launches)
@@ -194,7 +208,7 @@ def main() -> int:
                    "width": width, "method": "swept", "parallelism": "single-gpu"},
         "naive": {"value": naive_value, "ms_per_step": naive_ms,
                   "hbm_roofline_value": HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]},
-        "swept_over_naive": value / naive_value,
+        "swept_over_naive": value / naive_value if naive_value else None,
         "effective_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]),
         "roofline": roofline,
         "wall_ms_per_step": wall_ms,
