@@ -87,6 +87,9 @@ typedef void *sw_stream;
  *   width           : triangle width W in cells (swept only).  0 = library
  *                     choice.  Valid W: even, W >= 2, W divides n_cells,
  *                     n_cells / W >= 2, W <= sw_max_width(eq).
+ *   threads         : workgroup size of the swept phase kernels: 64, 128 or
+ *                     256 (0 = library choice: W rounded up to a multiple of
+ *                     64, at most 256).
  *   d_workspace     : device working arrays supplied by the caller (at least
  *                     sw_workspace_bytes() long, 256-byte aligned), or NULL
  *                     for the library's cached arrays.  Required when the
@@ -94,7 +97,7 @@ typedef void *sw_stream;
  *   workspace_bytes : size of d_workspace.                                  */
 typedef struct {
     int width;
-    int reserved0;
+    int threads;
     void *d_workspace;
     size_t workspace_bytes;
 } sw_opts;
@@ -159,6 +162,86 @@ int sw_phase_info(int64_t k, int64_t final_level, int width, int64_t *offset,
  * coordinates (empty when *lo >= *hi).  SW_ERR_ARG for invalid arguments. */
 int sw_phase_interval(int64_t k, int64_t final_level, int width, int64_t level, int *lo,
                       int *hi);
+
+/* ---- autotuner ---------------------------------------------------------------
+ * The paper recommends tuning the block width on a limited number of time
+ * steps before a long run, starting from wide blocks (Sec. 6).  sw_autotune
+ * times short swept solves on a scratch state (allocated and freed here) over
+ * every valid width that is a multiple of 64 (every valid width if there is
+ * none) and workgroup sizes 64/128/256, and records the fastest for
+ * (device architecture, eq, n_cells).  swept_solve and the batch use a
+ * recorded width whenever the caller gives none.  probe_steps = 0 picks
+ * enough steps for four phases at the widest candidate.  If the environment
+ * variable SWEPT_TUNE_CACHE names a file, recorded widths are appended to it
+ * and read back by later processes.  Not allowed during stream capture
+ * (SW_ERR_CAPTURE); synchronises `stream`. */
+int sw_autotune(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream, sw_opts *best,
+                double *best_ms_per_update);
+
+/* The recorded width (and workgroup size) of (current device, eq, n_cells);
+ * SW_ERR_UNSUPPORTED when none is recorded. */
+int sw_tuned_width(int eq, int64_t n_cells, int *width, int *threads);
+
+/* Forget every recorded width of this process (the cache file is kept). */
+void sw_tune_clear(void);
+
+/* ---- batched persistent launch -------------------------------------------------
+ * Many independent problems advanced by ONE launch of a persistent kernel,
+ * captured once into a hipGraph.  Work items (problem, phase, tile) are
+ * handed out in phase order by a global ticket; an item waits for the two
+ * tiles of the previous phase of its problem that overlap it (per-tile
+ * completion flags in device memory), runs the same tile-phase code as
+ * swept_solve, and publishes its flag.  Each problem ends bit-identical to
+ * swept_solve of that problem with the same width.  Every wait is bounded in
+ * time: a wait that exceeds the bound aborts the whole launch, which then
+ * reports SW_ERR_HIP from sw_batch_wait. */
+typedef struct {
+    int eq;          /* sw_equation                                          */
+    int width;       /* triangle width, 0 = tuned width, else library choice */
+    int64_t n_cells; /* >= 4                                                 */
+    int64_t n_steps; /* >= 0                                                 */
+    double dt, dx;   /* finite, > 0                                          */
+    void *d_state;   /* device state buffer laid out as for swept_solve; the
+                        problems' buffers must not overlap                   */
+} sw_problem;
+
+typedef struct {
+    int blocks_per_cu;     /* resident workgroups per CU, 0 = occupancy limit */
+    int reserved0;
+    int64_t wait_limit_us; /* bound of one dependency wait, 0 = 10 s           */
+} sw_batch_opts;
+
+typedef struct sw_batch_impl *sw_batch;
+
+/* Validate the problems, allocate every problem's working arrays and the
+ * work tables on the current device, and capture the launch into a graph.
+ * Synchronous; must not be called during stream capture.  opts may be NULL. */
+int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_opts *opts,
+                    sw_batch *out);
+
+/* Launch the batch graph on `stream` (asynchronous, allocates nothing). */
+int sw_batch_run(sw_batch batch, sw_stream stream);
+
+/* Synchronise `stream` and report whether the last run completed
+ * (SW_ERR_HIP if a dependency wait exceeded its bound). */
+int sw_batch_wait(sw_batch batch, sw_stream stream);
+
+/* Work items, resident workgroups and working-array bytes of a batch. */
+int sw_batch_info(sw_batch batch, int64_t *items, int *blocks, size_t *array_bytes);
+
+/* Width chosen for problem i (0 for an invalid index). */
+int sw_batch_width(sw_batch batch, int problem);
+
+/* Synchronise the device and free everything the batch owns. */
+void sw_batch_destroy(sw_batch batch);
+
+/* create + run + wait + destroy. */
+int swept_solve_batch(int n_problems, const sw_problem *problems, sw_stream stream);
+
+/* Previous-phase tiles that work item (phase, tile) of a batched problem
+ * with `tiles` tiles waits for (host mirror of the device rule, no HIP call):
+ * writes up to 3 tile indices to deps and returns their count. */
+int sw_batch_item_deps(int phase, int tile, int tiles, int single_phase, int *deps);
 
 /* Message of the last failed call on this thread ("" if none).  Valid until
  * the next library call on the same thread. */

@@ -37,8 +37,19 @@ class SweptError(RuntimeError):
 
 
 class sw_opts(ctypes.Structure):
-    _fields_ = [("width", ctypes.c_int), ("reserved0", ctypes.c_int),
+    _fields_ = [("width", ctypes.c_int), ("threads", ctypes.c_int),
                 ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class sw_problem(ctypes.Structure):
+    _fields_ = [("eq", ctypes.c_int), ("width", ctypes.c_int), ("n_cells", ctypes.c_int64),
+                ("n_steps", ctypes.c_int64), ("dt", ctypes.c_double), ("dx", ctypes.c_double),
+                ("d_state", ctypes.c_void_p)]
+
+
+class sw_batch_opts(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int), ("reserved0", ctypes.c_int),
+                ("wait_limit_us", ctypes.c_int64)]
 
 
 _lib = None
@@ -80,6 +91,29 @@ def load() -> ctypes.CDLL:
     lib.sw_last_error.restype = ctypes.c_char_p
     lib.sw_release.argtypes = []
     lib.sw_release.restype = None
+    lib.sw_autotune.argtypes = [i32, i64, i64, vp, ctypes.POINTER(sw_opts), ctypes.POINTER(d)]
+    lib.sw_autotune.restype = i32
+    lib.sw_tuned_width.argtypes = [i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.sw_tuned_width.restype = i32
+    lib.sw_tune_clear.argtypes = []
+    lib.sw_tune_clear.restype = None
+    lib.sw_batch_create.argtypes = [i32, ctypes.POINTER(sw_problem), ctypes.POINTER(sw_batch_opts),
+                                    ctypes.POINTER(vp)]
+    lib.sw_batch_create.restype = i32
+    lib.sw_batch_run.argtypes = [vp, vp]
+    lib.sw_batch_run.restype = i32
+    lib.sw_batch_wait.argtypes = [vp, vp]
+    lib.sw_batch_wait.restype = i32
+    lib.sw_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(sz)]
+    lib.sw_batch_info.restype = i32
+    lib.sw_batch_width.argtypes = [vp, i32]
+    lib.sw_batch_width.restype = i32
+    lib.sw_batch_destroy.argtypes = [vp]
+    lib.sw_batch_destroy.restype = None
+    lib.swept_solve_batch.argtypes = [i32, ctypes.POINTER(sw_problem), vp]
+    lib.swept_solve_batch.restype = i32
+    lib.sw_batch_item_deps.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i32)]
+    lib.sw_batch_item_deps.restype = i32
     _lib = lib
     return lib
 
@@ -88,10 +122,11 @@ def last_error() -> str:
     return load().sw_last_error().decode()
 
 
-def _opts(width: int = 0, workspace: int | None = None, workspace_bytes: int = 0):
+def _opts(width: int = 0, workspace: int | None = None, workspace_bytes: int = 0,
+          threads: int = 0):
     o = sw_opts()
     o.width = int(width)
-    o.reserved0 = 0
+    o.threads = int(threads)
     o.d_workspace = workspace
     o.workspace_bytes = int(workspace_bytes)
     return o
@@ -108,8 +143,8 @@ def naive_solve(eq, n_cells, n_steps, dt, dx, d_state, stream=None) -> int:
 
 
 def swept_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream=None, width=0,
-                   workspace=None, workspace_bytes=0) -> int:
-    o = _opts(width, workspace, workspace_bytes)
+                   workspace=None, workspace_bytes=0, threads=0) -> int:
+    o = _opts(width, workspace, workspace_bytes, threads)
     return load().swept_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream, ctypes.byref(o))
 
 
@@ -160,6 +195,93 @@ def sw_release() -> None:
     load().sw_release()
 
 
+# ---- autotuner -----------------------------------------------------------------
+
+def sw_autotune(eq, n_cells, probe_steps=0, stream=None):
+    """Returns (width, threads, ms_per_cell_update); raises on failure."""
+    best = sw_opts()
+    ms = ctypes.c_double()
+    rc = load().sw_autotune(eq, n_cells, probe_steps, stream, ctypes.byref(best), ctypes.byref(ms))
+    if rc:
+        raise SweptError(rc, last_error())
+    return best.width, best.threads, ms.value
+
+
+def sw_tuned_width(eq, n_cells):
+    """(width, threads) recorded for (current device, eq, n_cells), or None."""
+    w, t = ctypes.c_int(), ctypes.c_int()
+    rc = load().sw_tuned_width(eq, n_cells, ctypes.byref(w), ctypes.byref(t))
+    return (w.value, t.value) if rc == SW_OK else None
+
+
+def sw_tune_clear() -> None:
+    load().sw_tune_clear()
+
+
+# ---- batched persistent launch ----------------------------------------------------
+
+def problem_array(problems):
+    """List of dicts/tuples -> ctypes array of sw_problem."""
+    arr = (sw_problem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = sw_problem(*p) if isinstance(p, (tuple, list)) else sw_problem(**p)
+    return arr
+
+
+def sw_batch_item_deps(phase, tile, tiles, single_phase=0):
+    deps = (ctypes.c_int * 3)()
+    n = load().sw_batch_item_deps(phase, tile, tiles, single_phase, deps)
+    if n < 0:
+        raise SweptError(SW_ERR_ARG, "invalid item")
+    return list(deps[:n])
+
+
+class Batch:
+    """Owner of an sw_batch handle (see include/swept.h)."""
+
+    def __init__(self, problems, blocks_per_cu=0, wait_limit_us=0):
+        self._arr = problem_array(problems)
+        opts = sw_batch_opts(int(blocks_per_cu), 0, int(wait_limit_us))
+        h = ctypes.c_void_p()
+        rc = load().sw_batch_create(len(self._arr), self._arr, ctypes.byref(opts), ctypes.byref(h))
+        if rc:
+            raise SweptError(rc, last_error())
+        self.handle = h
+
+    def run(self, stream=None) -> None:
+        rc = load().sw_batch_run(self.handle, stream)
+        if rc:
+            raise SweptError(rc, last_error())
+
+    def wait(self, stream=None) -> int:
+        return load().sw_batch_wait(self.handle, stream)
+
+    def info(self):
+        items, blocks, nbytes = ctypes.c_int64(), ctypes.c_int(), ctypes.c_size_t()
+        load().sw_batch_info(self.handle, ctypes.byref(items), ctypes.byref(blocks),
+                             ctypes.byref(nbytes))
+        return items.value, blocks.value, nbytes.value
+
+    def width(self, i) -> int:
+        return load().sw_batch_width(self.handle, i)
+
+    def close(self) -> None:
+        if self.handle:
+            load().sw_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def swept_solve_batch(problems, stream=None) -> int:
+    arr = problem_array(problems)
+    return load().swept_solve_batch(len(arr), arr, stream)
+
+
 # ---- torch convenience -----------------------------------------------------
 
 def substeps(eq: int) -> int:
@@ -177,7 +299,7 @@ def state_rows(eq: int) -> int:
 
 
 def solve(eq: int, state, n_steps: int, dt: float, dx: float, method: str = "swept",
-          width: int = 0, workspace=None, stream=None) -> None:
+          width: int = 0, workspace=None, stream=None, threads: int = 0) -> None:
     """Advance a torch device tensor of shape (rows, n_cells) in place.
 
     ``rows`` is :func:`state_rows`; the dtype is float64 for *_F64 and float32
@@ -194,7 +316,8 @@ def solve(eq: int, state, n_steps: int, dt: float, dx: float, method: str = "swe
     ws_ptr = workspace.data_ptr() if workspace is not None else None
     ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     if method == "swept":
-        rc = swept_solve_ex(eq, n, n_steps, dt, dx, state.data_ptr(), handle, width, ws_ptr, ws_bytes)
+        rc = swept_solve_ex(eq, n, n_steps, dt, dx, state.data_ptr(), handle, width, ws_ptr,
+                            ws_bytes, threads)
     elif method == "naive":
         rc = naive_solve_ex(eq, n, n_steps, dt, dx, state.data_ptr(), handle, ws_ptr, ws_bytes)
     else:

@@ -13,9 +13,11 @@
 
 #include "../../include/swept.h"
 #include "geom.h"
+#include "host.h"
 #include "kernels.h"
 
-namespace {
+namespace sw {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -35,6 +37,8 @@ int ok()
     g_err.clear();
     return SW_OK;
 }
+
+const char *last_error() { return g_err.c_str(); }
 
 bool valid_eq(int eq) { return eq >= SW_HEAT_F64 && eq <= SW_EULER_F32; }
 bool is_euler(int eq) { return eq == SW_EULER_F64 || eq == SW_EULER_F32; }
@@ -64,6 +68,7 @@ int struct_bytes(int eq)
 }
 
 int preferred_width(int eq) { return is_euler(eq) ? 256 : 1024; }
+
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -221,10 +226,17 @@ int launched(hipError_t e, const char *what)
     return SW_OK;
 }
 
+} // namespace host
+} // namespace sw
+
+namespace {
+
+using namespace sw::host;
+
 // ---- the two methods ---------------------------------------------------------
 
 int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *state,
-              hipStream_t s, int w, void *ws)
+              hipStream_t s, int w, int threads, void *ws)
 {
     const int64_t final_level = steps * substeps(eq);
     const int64_t half = w / 2;
@@ -243,6 +255,7 @@ int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
         p.base = pr.base;
         p.j_first = pr.j_first;
         p.j_last = pr.j_last;
+        p.threads = threads;
         p.first = (k == 1);
         // A single phase (heat, one step) may not write the caller's state:
         // its tiles read their halos from that same state.  It writes the
@@ -336,6 +349,7 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
     if (rc)
         return rc;
     int w = 0;
+    int tuned_threads = 0;
     if (method == SW_METHOD_SWEPT) {
         if (o && o->width) {
             if (!width_ok(eq, n, o->width))
@@ -345,12 +359,14 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
                             o->width, (long long)n, max_width(eq));
             w = o->width;
         } else {
-            w = default_width(eq, n);
+            w = chosen_width(-1, eq, n, &tuned_threads);
             if (!w)
                 return fail(SW_ERR_UNSUPPORTED, "no valid triangle width for n_cells %lld",
                             (long long)n);
         }
     }
+    if (o && o->threads && o->threads != 64 && o->threads != 128 && o->threads != 256)
+        return fail(SW_ERR_ARG, "threads must be 0, 64, 128 or 256");
     if (o && o->d_workspace && ((uintptr_t)o->d_workspace & 255) != 0)
         return fail(SW_ERR_ARG, "workspace must be 256-byte aligned");
     if (steps == 0)
@@ -366,7 +382,9 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
     rc = get_workspace(dev, s, need, o, &ws);
     if (rc)
         return rc;
-    rc = (method == SW_METHOD_SWEPT) ? run_swept(eq, n, steps, dt, dx, state, s, w, ws)
+    const int threads = (o && o->threads) ? o->threads
+                        : (tuned_threads ? tuned_threads : sw::default_phase_threads(w));
+    rc = (method == SW_METHOD_SWEPT) ? run_swept(eq, n, steps, dt, dx, state, s, w, threads, ws)
                                      : run_naive(eq, n, steps, dt, dx, state, s, ws);
     return rc ? rc : ok();
 }
@@ -465,7 +483,7 @@ int sw_phase_interval(int64_t k, int64_t final_level, int width, int64_t level, 
     return ok();
 }
 
-const char *sw_last_error(void) { return g_err.c_str(); }
+const char *sw_last_error(void) { return sw::host::last_error(); }
 
 void sw_release(void)
 {

@@ -1,0 +1,198 @@
+// batch.hip -- persistent kernel of the batched swept launch (tables and
+// ordering described in batch.h).  One workgroup of 256 threads runs one
+// work item at a time with the same tile-phase bodies as the per-phase
+// kernels, so a problem solved in a batch is bit-identical to the same
+// problem solved alone with the same width.
+//
+// Every dependency wait is bounded in wall-clock time (s_memrealtime ticks):
+// a wait that exceeds the bound records status 1 and makes every workgroup
+// leave, so the launch always terminates.
+#include "batch.h"
+#include "kernels.h"
+#include "tile_euler.h"
+#include "tile_heat.h"
+
+namespace sw {
+namespace {
+
+constexpr int kBatchThreads = 256;
+
+__device__ __forceinline__ int load_acquire(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_release(int *p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// index of the segment holding item (segments sorted by start, first start 0)
+__device__ int64_t find_segment(const BatchSegment *seg, int64_t count, int64_t item)
+{
+    int64_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (seg[mid].start <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// copy-out of a single-phase problem: level 1 sits in slot 1 of ws0
+template <int NT>
+__device__ void copy_out(const BatchProblem &P, int tile)
+{
+    const int64_t c0 = (int64_t)tile * P.w;
+    if (P.eq == 0) {  // heat binary64: slot1 = ws0 + n doubles
+        const double *src = (const double *)P.ws0 + P.n;
+        double *dst = (double *)P.state;
+        for (int i = threadIdx.x; i < P.w; i += NT)
+            dst[c0 + i] = src[c0 + i];
+    } else {          // heat binary32: u1 = ws0 + n floats, c = ws0 + 2n floats
+        const float *src = (const float *)P.ws0;
+        float *dst = (float *)P.state;
+        for (int i = threadIdx.x; i < P.w; i += NT) {
+            dst[c0 + i] = src[P.n + c0 + i];
+            dst[P.n + c0 + i] = src[2 * P.n + c0 + i];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBatchThreads) k_batch_persistent(BatchTables b)
+{
+    extern __shared__ double lds[];
+    __shared__ long long s_item;
+    __shared__ int s_abort;
+    const int tid = threadIdx.x;
+
+    for (;;) {
+        if (tid == 0)
+            s_item = (long long)atomicAdd(b.ticket, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= b.n_items)
+            return;  // uniform: every thread read the same s_item
+        const BatchSegment seg = b.segments[find_segment(b.segments, b.n_segments, item)];
+        const BatchProblem &P = b.problems[seg.problem];
+        const int k = seg.phase;
+        const int t = (int)(item - seg.start);
+
+        if (tid == 0) {
+            int abort = 0;
+            int deps[3];
+            const int nd = batch_deps(k, t, P.tiles, P.single_phase, deps);
+            for (int d = 0; d < nd && !abort; ++d) {
+                const int *f = b.flags + P.flag_off + deps[d];
+                const long long t0 = __builtin_amdgcn_s_memrealtime();
+                while (load_acquire(f) < k - 1) {
+                    if (load_acquire(b.status) != 0 ||
+                        (long long)__builtin_amdgcn_s_memrealtime() - t0 > b.wait_limit) {
+                        store_release(b.status, 1);
+                        abort = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            s_abort = abort;
+        }
+        __syncthreads();
+        if (s_abort)
+            return;  // uniform
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+        if (P.single_phase && k == 2) {
+            copy_out<kBatchThreads>(P, t);
+        } else {
+            const int64_t half = P.w / 2;
+            const PhaseRange pr = phase_range(k, P.final_level, half);
+            TileJob jb;
+            jb.state = P.state;
+            jb.ws_in = (k % 2 == 0) ? P.ws0 : P.ws1;
+            jb.ws_out = (k % 2 == 1) ? P.ws0 : P.ws1;
+            jb.n = P.n;
+            jb.g0 = pr.offset + (int64_t)t * P.w - 1;
+            jb.base = pr.base;
+            jb.coef = P.coef;
+            jb.w = P.w;
+            jb.j_first = pr.j_first;
+            jb.j_last = pr.j_last;
+            jb.first = (k == 1);
+            jb.last = (k == P.phases) && !P.single_phase;
+            switch (P.eq) {
+            case 0: heat_f64_tile<kBatchThreads>(jb, lds); break;
+            case 1: heat_f32_tile<kBatchThreads>(jb, (float *)lds); break;
+            case 2: euler_f64_tile<kBatchThreads>(jb, lds); break;
+            default: euler_f32_tile<kBatchThreads>(jb, lds); break;
+            }
+        }
+        // publish: every thread's stores reach device scope before the flag
+        __threadfence();
+        __syncthreads();
+        if (tid == 0)
+            store_release(b.flags + P.flag_off + t, k);
+    }
+}
+
+// zero the ticket, the status word and every tile flag (a plain kernel, so
+// the sequence can be captured into a graph and replayed)
+__global__ void k_batch_reset(unsigned long long *ticket, int *status, int *flags, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *ticket = 0ull;
+        *status = 0;
+    }
+    for (int64_t j = i; j < count; j += (int64_t)gridDim.x * blockDim.x)
+        flags[j] = 0;
+}
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t count, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+hipError_t fill(T *p, int64_t count, T v, hipStream_t s)
+{
+    const int64_t b = (count + 255) / 256;
+    const unsigned blocks = (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s) { return fill(p, count, v, s); }
+hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s) { return fill(p, count, v, s); }
+
+int batch_threads() { return kBatchThreads; }
+
+hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent,
+                                                        kBatchThreads, lds_bytes);
+}
+
+hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, size_t lds_bytes,
+                        hipStream_t s)
+{
+    const int64_t rb = (n_flags + 255) / 256;
+    const unsigned reset_blocks = (unsigned)(rb < 1 ? 1 : (rb > 4096 ? 4096 : rb));
+    hipLaunchKernelGGL(k_batch_reset, dim3(reset_blocks), dim3(256), 0, s, t.ticket, t.status,
+                       t.flags, n_flags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_batch_persistent, dim3((unsigned)blocks), dim3(kBatchThreads), lds_bytes,
+                       s, t);
+    return hipGetLastError();
+}
+
+} // namespace sw

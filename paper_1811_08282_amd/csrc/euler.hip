@@ -1,160 +1,37 @@
-// euler.hip -- 1D Euler kernels: swept phases and classic sub-step kernels,
-// binary64 and binary32 (+ Kahan, binary64 islands).
-//
-// Scheme (Sec. 4.2: second-order finite volume with a minmod limiter; the
-// lengthened layout of Sec. 4.3 / Fig. 2b: a per-cell struct of Q0, Q1 and
-// the pressure ratio Pr, four three-point sub-steps per time step):
-//   sub-step 0  Pr_i = (p_{i+1} - p_i) / (p_i - p_{i-1})      from Q0
-//   sub-step 1  Q1_i = Q0_i + (lambda/2) (F_{i-1/2} - F_{i+1/2})  fluxes of Q0
-//   sub-step 2  Pr_i                                          from Q1
-//   sub-step 3  Q0_i = Q0_i + lambda (F_{i-1/2} - F_{i+1/2})     fluxes of Q1
-// Face i+1/2 between cells L = i and R = i+1: limited states
-//   U- = U_L + (phi(1/Pr_L)/2) (U_R - U_L),  U+ = U_R - (phi(Pr_R)/2) (U_R - U_L)
-// with phi(q) = max(0, min(q, 1)) (NaN -> 0), and the Rusanov flux
-//   F = (F(U-) + F(U+))/2 - (sigma/2) (U+ - U-),  sigma = max(|u-|+a-, |u+|+a+).
-// gamma = 1.4, gamma - 1 = 0.4 as literals; every expression is evaluated in
-// the written order (the library is built without contraction).
-//
-// A neighbour that is one level ahead never overwrites a field a cell still
-// needs (Pr is written only at sub-steps 0/2, Q1 at 1, Q0 at 3), which is why
-// one struct per cell carries both of its latest levels.
-//
-// Face sharing: inside a level every face flux is computed once into LDS and
-// used by both cells it separates; pressures likewise for the ratio.
-#include <math.h>
-
-#include "geom.h"
+// euler.hip -- 1D Euler kernels: the swept phase kernel (one workgroup per
+// tile, body in tile_euler.h) and the classic sub-step kernels, binary64 and
+// binary32 (+ Kahan, binary64 islands).  The classic kernels share each face
+// flux (and each pressure) between the two cells of a block that use it.
 #include "kernels.h"
+#include "tile_euler.h"
 
 namespace sw {
 namespace {
 
-constexpr double kGamma = 1.4;
-constexpr double kGm1 = 0.4;
 constexpr int kNaiveBlock = 256;
 
-__device__ __forceinline__ int64_t wrap_cell(int64_t g, int64_t n)
-{
-    if (g < 0)
-        return g + n;
-    if (g >= n)
-        return g - n;
-    return g;
-}
-
-__device__ __forceinline__ double limiter(double q)
-{
-    if (q > 0.0)
-        return q < 1.0 ? q : 1.0;
-    return 0.0;
-}
-
-__device__ __forceinline__ double ratio(double pm, double pc, double pp)
-{
-    return (pp - pc) / (pc - pm);
-}
-
-// ---- binary64 --------------------------------------------------------------
-
-__device__ __forceinline__ double pressure64(double rho, double m, double e)
-{
-    const double u = m / rho;
-    return kGm1 * (e - 0.5 * (m * u));
-}
-
-__device__ __forceinline__ void face64(double a0, double a1, double a2, double b0, double b1,
-                                       double b2, double pra, double prb, double &f0, double &f1,
-                                       double &f2)
-{
-    const double hl = 0.5 * limiter(1.0 / pra);
-    const double hr = 0.5 * limiter(prb);
-    const double d0 = b0 - a0, d1 = b1 - a1, d2 = b2 - a2;
-    const double l0 = a0 + hl * d0, l1 = a1 + hl * d1, l2 = a2 + hl * d2;
-    const double r0 = b0 - hr * d0, r1 = b1 - hr * d1, r2 = b2 - hr * d2;
-    const double vl = l1 / l0;
-    const double pl = kGm1 * (l2 - 0.5 * (l1 * vl));
-    const double vr = r1 / r0;
-    const double pr = kGm1 * (r2 - 0.5 * (r1 * vr));
-    const double al = sqrt((kGamma * pl) / l0);
-    const double ar = sqrt((kGamma * pr) / r0);
-    const double sl = fabs(vl) + al;
-    const double sr = fabs(vr) + ar;
-    const double hs = 0.5 * (sl > sr ? sl : sr);
-    f0 = 0.5 * (l1 + r1) - hs * (r0 - l0);
-    f1 = 0.5 * ((l1 * vl + pl) + (r1 * vr + pr)) - hs * (r1 - l1);
-    f2 = 0.5 * ((l2 + pl) * vl + (r2 + pr) * vr) - hs * (r2 - l2);
-}
-
-// LDS: q0[3][wp] q1[3][wp] pr[wp] tmp[3][wp]   (doubles, wp = w + 2)
-__global__ void __launch_bounds__(256)
+template <int NT>
+__global__ void __launch_bounds__(NT)
 k_euler_f64_phase(double *__restrict__ state, const double *__restrict__ ws_in,
                   double *__restrict__ ws_out, int64_t n, int w, int64_t offset, int64_t base,
                   int j_first, int j_last, double lam, int first, int last)
 {
     extern __shared__ double lds[];
-    const int wp = w + 2;
-    double *q0 = lds;
-    double *q1 = lds + 3 * wp;
-    double *pr = lds + 6 * wp;
-    double *tmp = lds + 7 * wp;
-    const int64_t g0 = offset + (int64_t)blockIdx.x * w - 1;
+    TileJob jb{state, ws_in, ws_out, n, offset + (int64_t)blockIdx.x * w - 1, base, lam, w,
+               j_first, j_last, first, last};
+    euler_f64_tile<NT>(jb, lds);
+}
 
-    for (int i = threadIdx.x; i < wp; i += blockDim.x) {
-        const int64_t g = wrap_cell(g0 + i, n);
-        if (first) {
-            for (int k = 0; k < 3; ++k)
-                q0[k * wp + i] = state[k * n + g];
-        } else {
-            for (int k = 0; k < 7; ++k)
-                lds[k * wp + i] = ws_in[k * n + g];
-        }
-    }
-    __syncthreads();
-
-    const double half_lam = 0.5 * lam;
-    for (int j = j_first; j <= j_last; ++j) {
-        const int a = window_margin(j);
-        const int lo = a + 1, hi = w - a + 1;  // active LDS indices [lo, hi)
-        const int t = (int)((base + j - 1) & 3);
-        const double *q = (t < 2) ? q0 : q1;
-        if ((t & 1) == 0) {
-            for (int i = lo - 1 + threadIdx.x; i < hi + 1; i += blockDim.x)
-                tmp[i] = pressure64(q[i], q[wp + i], q[2 * wp + i]);
-            __syncthreads();
-            for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
-                pr[i] = ratio(tmp[i - 1], tmp[i], tmp[i + 1]);
-            __syncthreads();
-        } else {
-            // tmp[k][i]: flux through the face between LDS cells i-1 and i
-            for (int i = lo + threadIdx.x; i < hi + 1; i += blockDim.x)
-                face64(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
-                       pr[i - 1], pr[i], tmp[i], tmp[wp + i], tmp[2 * wp + i]);
-            __syncthreads();
-            if (t == 1) {
-                for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
-                    for (int k = 0; k < 3; ++k)
-                        q1[k * wp + i] =
-                            q0[k * wp + i] + half_lam * (tmp[k * wp + i] - tmp[k * wp + i + 1]);
-            } else {
-                for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
-                    for (int k = 0; k < 3; ++k)
-                        q0[k * wp + i] =
-                            q0[k * wp + i] + lam * (tmp[k * wp + i] - tmp[k * wp + i + 1]);
-            }
-            __syncthreads();
-        }
-    }
-
-    for (int i = 1 + threadIdx.x; i <= w; i += blockDim.x) {
-        const int64_t g = wrap_cell(g0 + i, n);
-        if (last) {
-            for (int k = 0; k < 3; ++k)
-                state[k * n + g] = q0[k * wp + i];
-        } else {
-            for (int k = 0; k < 7; ++k)
-                ws_out[k * n + g] = lds[k * wp + i];
-        }
-    }
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_euler_f32_phase(float *__restrict__ state, const void *__restrict__ ws_in,
+                  void *__restrict__ ws_out, int64_t n, int w, int64_t offset, int64_t base,
+                  int j_first, int j_last, float lam, int first, int last)
+{
+    extern __shared__ double ldsd[];
+    TileJob jb{state, ws_in, ws_out, n, offset + (int64_t)blockIdx.x * w - 1, base, (double)lam,
+               w, j_first, j_last, first, last};
+    euler_f32_tile<NT>(jb, ldsd);
 }
 
 // Classic pressure-ratio sub-step: q (3n) -> pr (n).  Block-local pressures.
@@ -202,133 +79,6 @@ k_euler_f64_naive_flux(int t, double *__restrict__ q0, double *__restrict__ q1,
     } else {
         for (int k = 0; k < 3; ++k)
             q0[k * n + g] = q0[k * n + g] + lam * (f[k][i] - f[k][i + 1]);
-    }
-}
-
-// ---- binary32 with binary64 islands ------------------------------------------
-
-__device__ __forceinline__ double pressure32(float rho, float m, float e)
-{
-    const double dr = (double)rho, dm = (double)m, de = (double)e;
-    const double u = dm / dr;
-    return kGm1 * (de - 0.5 * (dm * u));
-}
-
-__device__ __forceinline__ void face32(float a0, float a1, float a2, float b0, float b1, float b2,
-                                       double pra, double prb, float &f0, float &f1, float &f2)
-{
-    const float hl = 0.5f * (float)limiter(1.0 / pra);
-    const float hr = 0.5f * (float)limiter(prb);
-    const float d0 = b0 - a0, d1 = b1 - a1, d2 = b2 - a2;
-    const float l0 = a0 + hl * d0, l1 = a1 + hl * d1, l2 = a2 + hl * d2;
-    const float r0 = b0 - hr * d0, r1 = b1 - hr * d1, r2 = b2 - hr * d2;
-    const double rl = (double)l0, ml = (double)l1, el = (double)l2;
-    const double rr = (double)r0, mr = (double)r1, er = (double)r2;
-    const double vl64 = ml / rl, vr64 = mr / rr;
-    const double pl64 = kGm1 * (el - 0.5 * (ml * vl64));
-    const double pr64 = kGm1 * (er - 0.5 * (mr * vr64));
-    const double al64 = sqrt((kGamma * pl64) / rl);
-    const double ar64 = sqrt((kGamma * pr64) / rr);
-    const float vl = (float)vl64, pl = (float)pl64, al = (float)al64;
-    const float vr = (float)vr64, pr = (float)pr64, ar = (float)ar64;
-    const float sl = fabsf(vl) + al;
-    const float sr = fabsf(vr) + ar;
-    const float hs = 0.5f * (sl > sr ? sl : sr);
-    f0 = 0.5f * (l1 + r1) - hs * (r0 - l0);
-    f1 = 0.5f * ((l1 * vl + pl) + (r1 * vr + pr)) - hs * (r1 - l1);
-    f2 = 0.5f * ((l2 + pl) * vl + (r2 + pr) * vr) - hs * (r2 - l2);
-}
-
-__device__ __forceinline__ float kahan_add(float q, float d, float &c)
-{
-    const float y = d - c;
-    const float t = q + y;
-    c = (t - q) - y;
-    return t;
-}
-
-// LDS: pr[wp] (double), tmp[3][wp] (float; reused as wp doubles for the
-// pressures), q0[3][wp], c[3][wp], q1[3][wp] (float).
-// HBM working array: q0[3][n], c[3][n], q1[3][n] floats, then pr[n] doubles.
-__global__ void __launch_bounds__(256)
-k_euler_f32_phase(float *__restrict__ state, const char *__restrict__ ws_in,
-                  char *__restrict__ ws_out, int64_t n, int w, int64_t offset, int64_t base,
-                  int j_first, int j_last, float lam, int first, int last)
-{
-    extern __shared__ double ldsd[];
-    const int wp = w + 2;
-    double *pr = ldsd;
-    double *ptmp = ldsd + wp;
-    float *ftmp = (float *)(ldsd + wp);
-    float *fst = (float *)(ldsd + wp) + 3 * wp;  // q0[3], c[3], q1[3]
-    float *q0 = fst;
-    float *cc = fst + 3 * wp;
-    float *q1 = fst + 6 * wp;
-    const int64_t g0 = offset + (int64_t)blockIdx.x * w - 1;
-    const float *win = (const float *)ws_in;
-    const double *win_pr = (const double *)(ws_in + 36 * n);
-
-    for (int i = threadIdx.x; i < wp; i += blockDim.x) {
-        const int64_t g = wrap_cell(g0 + i, n);
-        if (first) {
-            for (int k = 0; k < 6; ++k)
-                fst[k * wp + i] = state[k * n + g];
-        } else {
-            for (int k = 0; k < 9; ++k)
-                fst[k * wp + i] = win[k * n + g];
-            pr[i] = win_pr[g];
-        }
-    }
-    __syncthreads();
-
-    const float half_lam = 0.5f * lam;
-    for (int j = j_first; j <= j_last; ++j) {
-        const int a = window_margin(j);
-        const int lo = a + 1, hi = w - a + 1;
-        const int t = (int)((base + j - 1) & 3);
-        const float *q = (t < 2) ? q0 : q1;
-        if ((t & 1) == 0) {
-            for (int i = lo - 1 + threadIdx.x; i < hi + 1; i += blockDim.x)
-                ptmp[i] = pressure32(q[i], q[wp + i], q[2 * wp + i]);
-            __syncthreads();
-            for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
-                pr[i] = ratio(ptmp[i - 1], ptmp[i], ptmp[i + 1]);
-            __syncthreads();
-        } else {
-            for (int i = lo + threadIdx.x; i < hi + 1; i += blockDim.x)
-                face32(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
-                       pr[i - 1], pr[i], ftmp[i], ftmp[wp + i], ftmp[2 * wp + i]);
-            __syncthreads();
-            if (t == 1) {
-                for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
-                    for (int k = 0; k < 3; ++k)
-                        q1[k * wp + i] =
-                            q0[k * wp + i] + half_lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]);
-            } else {
-                for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
-                    for (int k = 0; k < 3; ++k) {
-                        float c = cc[k * wp + i];
-                        q0[k * wp + i] = kahan_add(
-                            q0[k * wp + i], lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]), c);
-                        cc[k * wp + i] = c;
-                    }
-            }
-            __syncthreads();
-        }
-    }
-
-    float *wout = (float *)ws_out;
-    double *wout_pr = (double *)(ws_out + 36 * n);
-    for (int i = 1 + threadIdx.x; i <= w; i += blockDim.x) {
-        const int64_t g = wrap_cell(g0 + i, n);
-        if (last) {
-            for (int k = 0; k < 6; ++k)
-                state[k * n + g] = fst[k * wp + i];
-        } else {
-            for (int k = 0; k < 9; ++k)
-                wout[k * n + g] = fst[k * wp + i];
-            wout_pr[g] = pr[i];
-        }
     }
 }
 
@@ -381,10 +131,17 @@ k_euler_f32_naive_flux(int t, float *__restrict__ q0c, float *__restrict__ q1,
     }
 }
 
-int phase_threads(int w)
+template <typename K64, typename K128, typename K256, typename... Args>
+hipError_t launch_by_threads(int nt, K64 k64, K128 k128, K256 k256, dim3 grid, size_t lds,
+                             hipStream_t s, Args... args)
 {
-    int t = ((w + 63) / 64) * 64;
-    return t < 64 ? 64 : (t > 256 ? 256 : t);
+    if (nt == 64)
+        hipLaunchKernelGGL(k64, grid, dim3(64), lds, s, args...);
+    else if (nt == 128)
+        hipLaunchKernelGGL(k128, grid, dim3(128), lds, s, args...);
+    else
+        hipLaunchKernelGGL(k256, grid, dim3(256), lds, s, args...);
+    return hipGetLastError();
 }
 
 } // namespace
@@ -393,10 +150,10 @@ hipError_t euler_f64_swept_phase(const PhaseLaunch &p, double *state, const doub
                                  double *ws_out, double lam, hipStream_t s)
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellEulerF64;
-    hipLaunchKernelGGL(k_euler_f64_phase, dim3((unsigned)(p.n / p.w)), dim3(phase_threads(p.w)),
-                       lds, s, state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first,
-                       p.j_last, lam, (int)p.first, (int)p.last);
-    return hipGetLastError();
+    return launch_by_threads(p.threads, k_euler_f64_phase<64>, k_euler_f64_phase<128>,
+                             k_euler_f64_phase<256>, dim3((unsigned)(p.n / p.w)), lds, s, state,
+                             ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+                             (int)p.first, (int)p.last);
 }
 
 hipError_t euler_f64_naive_substep(int t, double *q0, double *q1, double *pr, int64_t n,
@@ -416,10 +173,10 @@ hipError_t euler_f32_swept_phase(const PhaseLaunch &p, float *state, const void 
                                  void *ws_out, float lam, hipStream_t s)
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellEulerF32;
-    hipLaunchKernelGGL(k_euler_f32_phase, dim3((unsigned)(p.n / p.w)), dim3(phase_threads(p.w)),
-                       lds, s, state, (const char *)ws_in, (char *)ws_out, p.n, p.w, p.offset,
-                       p.base, p.j_first, p.j_last, lam, (int)p.first, (int)p.last);
-    return hipGetLastError();
+    return launch_by_threads(p.threads, k_euler_f32_phase<64>, k_euler_f32_phase<128>,
+                             k_euler_f32_phase<256>, dim3((unsigned)(p.n / p.w)), lds, s, state,
+                             ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+                             (int)p.first, (int)p.last);
 }
 
 hipError_t euler_f32_naive_substep(int t, float *q0c, float *q1, double *pr, int64_t n, float lam,

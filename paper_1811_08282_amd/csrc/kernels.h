@@ -32,7 +32,15 @@ struct PhaseLaunch {
     int j_first, j_last;
     bool first;       // reads the caller's state (level 0 of this call)
     bool last;        // writes the caller's state (final level)
+    int threads;      // workgroup size: 64, 128 or 256
 };
+
+// Default workgroup size of a swept phase for tile width w.
+inline int default_phase_threads(int w)
+{
+    const int t = ((w + 63) / 64) * 64;
+    return t < 64 ? 64 : (t > 256 ? 256 : t);
+}
 
 // Heat, binary64.  state: u[n]; ws_in / ws_out: working arrays of 2n doubles.
 hipError_t heat_f64_swept_phase(const PhaseLaunch &p, double *state, const double *ws_in,

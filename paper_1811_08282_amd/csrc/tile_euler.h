@@ -1,0 +1,283 @@
+// tile_euler.h -- Euler cell arithmetic and one swept tile-phase of the 1D
+// Euler equations, as device functions.
+//
+// Scheme (Sec. 4.2: second-order finite volume with a minmod limiter; the
+// lengthened layout of Sec. 4.3 / Fig. 2b: a per-cell struct of Q0, Q1 and
+// the pressure ratio Pr, four three-point sub-steps per time step):
+//   sub-step 0  Pr_i = (p_{i+1} - p_i) / (p_i - p_{i-1})      from Q0
+//   sub-step 1  Q1_i = Q0_i + (lambda/2) (F_{i-1/2} - F_{i+1/2})  fluxes of Q0
+//   sub-step 2  Pr_i                                          from Q1
+//   sub-step 3  Q0_i = Q0_i + lambda (F_{i-1/2} - F_{i+1/2})     fluxes of Q1
+// Face i+1/2 between cells L = i and R = i+1: limited states
+//   U- = U_L + (phi(1/Pr_L)/2) (U_R - U_L),  U+ = U_R - (phi(Pr_R)/2) (U_R - U_L)
+// with phi(q) = max(0, min(q, 1)) (NaN -> 0), and the Rusanov flux
+//   F = (F(U-) + F(U+))/2 - (sigma/2) (U+ - U-),  sigma = max(|u-|+a-, |u+|+a+).
+// gamma = 1.4, gamma - 1 = 0.4 as literals; every expression is evaluated in
+// the written order (the library is built without contraction).
+//
+// A neighbour that is one level ahead never overwrites a field a cell still
+// needs (Pr is written only at sub-steps 0/2, Q1 at 1, Q0 at 3), which is why
+// one struct per cell carries both of its latest levels.
+//
+// Face sharing: inside a level every face flux is computed once into LDS and
+// used by both cells it separates; pressures likewise for the ratio.
+#pragma once
+
+#include <math.h>
+
+#include "geom.h"
+#include "tile_job.h"
+
+namespace sw {
+
+constexpr double kGamma = 1.4;
+constexpr double kGm1 = 0.4;
+
+__device__ __forceinline__ double limiter(double q)
+{
+    if (q > 0.0)
+        return q < 1.0 ? q : 1.0;
+    return 0.0;
+}
+
+__device__ __forceinline__ double ratio(double pm, double pc, double pp)
+{
+    return (pp - pc) / (pc - pm);
+}
+
+// ---- binary64 ----------------------------------------------------------------
+
+__device__ __forceinline__ double pressure64(double rho, double m, double e)
+{
+    const double u = m / rho;
+    return kGm1 * (e - 0.5 * (m * u));
+}
+
+__device__ __forceinline__ void face64(double a0, double a1, double a2, double b0, double b1,
+                                       double b2, double pra, double prb, double &f0, double &f1,
+                                       double &f2)
+{
+    const double hl = 0.5 * limiter(1.0 / pra);
+    const double hr = 0.5 * limiter(prb);
+    const double d0 = b0 - a0, d1 = b1 - a1, d2 = b2 - a2;
+    const double l0 = a0 + hl * d0, l1 = a1 + hl * d1, l2 = a2 + hl * d2;
+    const double r0 = b0 - hr * d0, r1 = b1 - hr * d1, r2 = b2 - hr * d2;
+    const double vl = l1 / l0;
+    const double pl = kGm1 * (l2 - 0.5 * (l1 * vl));
+    const double vr = r1 / r0;
+    const double pr = kGm1 * (r2 - 0.5 * (r1 * vr));
+    const double al = sqrt((kGamma * pl) / l0);
+    const double ar = sqrt((kGamma * pr) / r0);
+    const double sl = fabs(vl) + al;
+    const double sr = fabs(vr) + ar;
+    const double hs = 0.5 * (sl > sr ? sl : sr);
+    f0 = 0.5 * (l1 + r1) - hs * (r0 - l0);
+    f1 = 0.5 * ((l1 * vl + pl) + (r1 * vr + pr)) - hs * (r1 - l1);
+    f2 = 0.5 * ((l2 + pl) * vl + (r2 + pr) * vr) - hs * (r2 - l2);
+}
+
+// LDS: q0[3][wp] q1[3][wp] pr[wp] tmp[3][wp]   (doubles, wp = w + 2)
+// ws layout: Q0[3][n], Q1[3][n], Pr[n] (doubles)
+template <int NT>
+__device__ __forceinline__ void euler_f64_tile(const TileJob &jb, double *lds)
+{
+    const int w = jb.w;
+    const int wp = w + 2;
+    const int64_t n = jb.n;
+    double *q0 = lds;
+    double *q1 = lds + 3 * wp;
+    double *pr = lds + 6 * wp;
+    double *tmp = lds + 7 * wp;
+    double *state = (double *)jb.state;
+    const double *ws_in = (const double *)jb.ws_in;
+    double *ws_out = (double *)jb.ws_out;
+    const int tid = threadIdx.x;
+
+    for (int i = tid; i < wp; i += NT) {
+        const int64_t g = wrap_cell(jb.g0 + i, n);
+        if (jb.first) {
+            for (int k = 0; k < 3; ++k)
+                q0[k * wp + i] = state[k * n + g];
+        } else {
+            for (int k = 0; k < 7; ++k)
+                lds[k * wp + i] = ws_in[k * n + g];
+        }
+    }
+    __syncthreads();
+
+    const double lam = jb.coef;
+    const double half_lam = 0.5 * lam;
+    for (int j = jb.j_first; j <= jb.j_last; ++j) {
+        const int a = window_margin(j);
+        const int lo = a + 1, hi = w - a + 1;  // active LDS indices [lo, hi)
+        const int t = (int)((jb.base + j - 1) & 3);
+        const double *q = (t < 2) ? q0 : q1;
+        if ((t & 1) == 0) {
+            for (int i = lo - 1 + tid; i < hi + 1; i += NT)
+                tmp[i] = pressure64(q[i], q[wp + i], q[2 * wp + i]);
+            __syncthreads();
+            for (int i = lo + tid; i < hi; i += NT)
+                pr[i] = ratio(tmp[i - 1], tmp[i], tmp[i + 1]);
+            __syncthreads();
+        } else {
+            // tmp[k][i]: flux through the face between LDS cells i-1 and i
+            for (int i = lo + tid; i < hi + 1; i += NT)
+                face64(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
+                       pr[i - 1], pr[i], tmp[i], tmp[wp + i], tmp[2 * wp + i]);
+            __syncthreads();
+            if (t == 1) {
+                for (int i = lo + tid; i < hi; i += NT)
+                    for (int k = 0; k < 3; ++k)
+                        q1[k * wp + i] =
+                            q0[k * wp + i] + half_lam * (tmp[k * wp + i] - tmp[k * wp + i + 1]);
+            } else {
+                for (int i = lo + tid; i < hi; i += NT)
+                    for (int k = 0; k < 3; ++k)
+                        q0[k * wp + i] =
+                            q0[k * wp + i] + lam * (tmp[k * wp + i] - tmp[k * wp + i + 1]);
+            }
+            __syncthreads();
+        }
+    }
+
+    for (int i = 1 + tid; i <= w; i += NT) {
+        const int64_t g = wrap_cell(jb.g0 + i, n);
+        if (jb.last) {
+            for (int k = 0; k < 3; ++k)
+                state[k * n + g] = q0[k * wp + i];
+        } else {
+            for (int k = 0; k < 7; ++k)
+                ws_out[k * n + g] = lds[k * wp + i];
+        }
+    }
+}
+
+// ---- binary32 with binary64 islands ------------------------------------------
+
+__device__ __forceinline__ double pressure32(float rho, float m, float e)
+{
+    const double dr = (double)rho, dm = (double)m, de = (double)e;
+    const double u = dm / dr;
+    return kGm1 * (de - 0.5 * (dm * u));
+}
+
+__device__ __forceinline__ void face32(float a0, float a1, float a2, float b0, float b1, float b2,
+                                       double pra, double prb, float &f0, float &f1, float &f2)
+{
+    const float hl = 0.5f * (float)limiter(1.0 / pra);
+    const float hr = 0.5f * (float)limiter(prb);
+    const float d0 = b0 - a0, d1 = b1 - a1, d2 = b2 - a2;
+    const float l0 = a0 + hl * d0, l1 = a1 + hl * d1, l2 = a2 + hl * d2;
+    const float r0 = b0 - hr * d0, r1 = b1 - hr * d1, r2 = b2 - hr * d2;
+    const double rl = (double)l0, ml = (double)l1, el = (double)l2;
+    const double rr = (double)r0, mr = (double)r1, er = (double)r2;
+    const double vl64 = ml / rl, vr64 = mr / rr;
+    const double pl64 = kGm1 * (el - 0.5 * (ml * vl64));
+    const double pr64 = kGm1 * (er - 0.5 * (mr * vr64));
+    const double al64 = sqrt((kGamma * pl64) / rl);
+    const double ar64 = sqrt((kGamma * pr64) / rr);
+    const float vl = (float)vl64, pl = (float)pl64, al = (float)al64;
+    const float vr = (float)vr64, pr = (float)pr64, ar = (float)ar64;
+    const float sl = fabsf(vl) + al;
+    const float sr = fabsf(vr) + ar;
+    const float hs = 0.5f * (sl > sr ? sl : sr);
+    f0 = 0.5f * (l1 + r1) - hs * (r0 - l0);
+    f1 = 0.5f * ((l1 * vl + pl) + (r1 * vr + pr)) - hs * (r1 - l1);
+    f2 = 0.5f * ((l2 + pl) * vl + (r2 + pr) * vr) - hs * (r2 - l2);
+}
+
+__device__ __forceinline__ float kahan_add(float q, float d, float &c)
+{
+    const float y = d - c;
+    const float t = q + y;
+    c = (t - q) - y;
+    return t;
+}
+
+// LDS: pr[wp] (double), tmp[3][wp] (float; reused as wp doubles for the
+// pressures), q0[3][wp], c[3][wp], q1[3][wp] (float).
+// ws layout: q0[3][n], c[3][n], q1[3][n] floats, then pr[n] doubles at byte 36n.
+template <int NT>
+__device__ __forceinline__ void euler_f32_tile(const TileJob &jb, double *ldsd)
+{
+    const int w = jb.w;
+    const int wp = w + 2;
+    const int64_t n = jb.n;
+    double *pr = ldsd;
+    double *ptmp = ldsd + wp;
+    float *ftmp = (float *)(ldsd + wp);
+    float *fst = (float *)(ldsd + wp) + 3 * wp;  // q0[3], c[3], q1[3]
+    float *q0 = fst;
+    float *cc = fst + 3 * wp;
+    float *q1 = fst + 6 * wp;
+    float *state = (float *)jb.state;
+    const float *win = (const float *)jb.ws_in;
+    const double *win_pr = (const double *)((const char *)jb.ws_in + 36 * n);
+    float *wout = (float *)jb.ws_out;
+    double *wout_pr = (double *)((char *)jb.ws_out + 36 * n);
+    const int tid = threadIdx.x;
+
+    for (int i = tid; i < wp; i += NT) {
+        const int64_t g = wrap_cell(jb.g0 + i, n);
+        if (jb.first) {
+            for (int k = 0; k < 6; ++k)
+                fst[k * wp + i] = state[k * n + g];
+        } else {
+            for (int k = 0; k < 9; ++k)
+                fst[k * wp + i] = win[k * n + g];
+            pr[i] = win_pr[g];
+        }
+    }
+    __syncthreads();
+
+    const float lam = (float)jb.coef;
+    const float half_lam = 0.5f * lam;
+    for (int j = jb.j_first; j <= jb.j_last; ++j) {
+        const int a = window_margin(j);
+        const int lo = a + 1, hi = w - a + 1;
+        const int t = (int)((jb.base + j - 1) & 3);
+        const float *q = (t < 2) ? q0 : q1;
+        if ((t & 1) == 0) {
+            for (int i = lo - 1 + tid; i < hi + 1; i += NT)
+                ptmp[i] = pressure32(q[i], q[wp + i], q[2 * wp + i]);
+            __syncthreads();
+            for (int i = lo + tid; i < hi; i += NT)
+                pr[i] = ratio(ptmp[i - 1], ptmp[i], ptmp[i + 1]);
+            __syncthreads();
+        } else {
+            for (int i = lo + tid; i < hi + 1; i += NT)
+                face32(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
+                       pr[i - 1], pr[i], ftmp[i], ftmp[wp + i], ftmp[2 * wp + i]);
+            __syncthreads();
+            if (t == 1) {
+                for (int i = lo + tid; i < hi; i += NT)
+                    for (int k = 0; k < 3; ++k)
+                        q1[k * wp + i] =
+                            q0[k * wp + i] + half_lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]);
+            } else {
+                for (int i = lo + tid; i < hi; i += NT)
+                    for (int k = 0; k < 3; ++k) {
+                        float c = cc[k * wp + i];
+                        q0[k * wp + i] = kahan_add(
+                            q0[k * wp + i], lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]), c);
+                        cc[k * wp + i] = c;
+                    }
+            }
+            __syncthreads();
+        }
+    }
+
+    for (int i = 1 + tid; i <= w; i += NT) {
+        const int64_t g = wrap_cell(jb.g0 + i, n);
+        if (jb.last) {
+            for (int k = 0; k < 6; ++k)
+                state[k * n + g] = fst[k * wp + i];
+        } else {
+            for (int k = 0; k < 9; ++k)
+                wout[k * n + g] = fst[k * wp + i];
+            wout_pr[g] = pr[i];
+        }
+    }
+}
+
+} // namespace sw

@@ -1,0 +1,193 @@
+"""GPU tests of the batched persistent launch and of the autotuner.
+
+A problem solved inside a batch must be bit-identical to the same problem
+solved alone by swept_solve with the same width (the same tile-phase code
+runs in both), and hence to the oracle.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1811_08282_amd as sw
+from paper_1811_08282_amd.workloads import heat_ic, sod_tiled
+from gpu_util import announce, pack, run
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _ic(eq, n, seed):
+    if eq in (sw.HEAT_F64, sw.HEAT_F32):
+        return heat_ic(n, seed)
+    return sod_tiled(n, n)
+
+
+def _coef(eq):
+    return (0.25, 1.0) if eq in (sw.HEAT_F64, sw.HEAT_F32) else (0.1, 1.0)
+
+
+def _problems(specs):
+    """specs: (eq, n, steps, width, seed) -> (device tensors, host ICs, sw_problem dicts)"""
+    import torch
+    tensors, hosts, probs = [], [], []
+    for eq, n, steps, width, seed in specs:
+        host = pack(eq, _ic(eq, n, seed))
+        t = torch.from_numpy(np.ascontiguousarray(host)).cuda()
+        dt, dx = _coef(eq)
+        tensors.append(t)
+        hosts.append(host)
+        probs.append(dict(eq=eq, width=width, n_cells=n, n_steps=steps, dt=dt, dx=dx,
+                          d_state=t.data_ptr()))
+    torch.cuda.synchronize()
+    return tensors, hosts, probs
+
+
+MIXED = [
+    (sw.HEAT_F64, 1024, 300, 64, 1),
+    (sw.HEAT_F32, 2048, 1, 128, 2),      # single phase: copy-out items
+    (sw.EULER_F64, 2048, 50, 256, 3),
+    (sw.EULER_F32, 1024, 30, 64, 4),
+    (sw.HEAT_F64, 4096, 0, 64, 5),       # no work
+    (sw.HEAT_F64, 1000, 77, 40, 6),      # ragged width
+    (sw.EULER_F64, 512, 9, 2, 7),        # width 2: one level per phase
+    (sw.HEAT_F32, 8192, 333, 1024, 8),
+]
+
+
+def test_mixed_batch_equals_individual_swept_and_oracle():
+    import torch
+    tensors, hosts, probs = _problems(MIXED)
+    announce("batch mixed", len(probs))
+    b = sw.Batch(probs)
+    items, blocks, nbytes = b.info()
+    assert items > 0 and blocks > 0
+    b.run(torch.cuda.current_stream().cuda_stream)
+    assert b.wait(torch.cuda.current_stream().cuda_stream) == sw.SW_OK, sw.last_error()
+    for (eq, n, steps, width, seed), t, host in zip(MIXED, tensors, hosts):
+        got = t.cpu().numpy()
+        dt, dx = _coef(eq)
+        announce("batch check", eq, n, steps, width)
+        alone = run(eq, host, steps, dt, dx, "swept", width=width)
+        assert np.array_equal(got, alone), (eq, n, steps, width)
+        if eq == sw.HEAT_F64:
+            assert np.array_equal(got[0], oracle.heat_f64(host[0], steps, dt / dx ** 2))
+        elif eq == sw.EULER_F64:
+            assert np.array_equal(got, oracle.euler_f64(host, steps, dt / dx))
+        elif eq == sw.HEAT_F32:
+            u, c = oracle.heat_f32(host[0], host[1], steps, dt / dx ** 2)
+            assert np.array_equal(got[0], u) and np.array_equal(got[1], c)
+        else:
+            q, c = oracle.euler_f32(host[:3], host[3:], steps, dt / dx)
+            assert np.array_equal(got[:3], q) and np.array_equal(got[3:], c)
+    b.close()
+
+
+def test_graph_replays_match_eager_runs():
+    """Replay the captured graph three times with eager solves and host
+    synchronisation between the replays; every replay must match."""
+    import torch
+    specs = [(sw.HEAT_F64, 2048, 97, 128, 11), (sw.EULER_F64, 1024, 13, 64, 12),
+             (sw.HEAT_F32, 1024, 40, 64, 13)]
+    tensors, hosts, probs = _problems(specs)
+    b = sw.Batch(probs)
+    eager = [h.copy() for h in hosts]
+    stream = torch.cuda.current_stream().cuda_stream
+    for rep in range(3):
+        announce("batch replay", rep)
+        b.run(stream)
+        assert b.wait(stream) == sw.SW_OK, sw.last_error()
+        for i, (eq, n, steps, width, seed) in enumerate(specs):
+            dt, dx = _coef(eq)
+            eager[i] = run(eq, eager[i], steps, dt, dx, "swept", width=width)
+            assert np.array_equal(tensors[i].cpu().numpy(), eager[i]), (rep, i)
+    b.close()
+
+
+def test_default_widths_and_one_shot_entry_point():
+    import torch
+    specs = [(sw.HEAT_F64, 256 * 5, 50, 0, 21), (sw.EULER_F32, 256 * 6, 20, 0, 22)]
+    tensors, hosts, probs = _problems(specs)
+    announce("batch one-shot")
+    assert sw.swept_solve_batch(probs, torch.cuda.current_stream().cuda_stream) == sw.SW_OK
+    for (eq, n, steps, width, seed), t, host in zip(specs, tensors, hosts):
+        dt, dx = _coef(eq)
+        alone = run(eq, host, steps, dt, dx, "swept")  # the same default width
+        assert np.array_equal(t.cpu().numpy(), alone)
+
+
+def test_bounded_wait_aborts_cleanly():
+    """A 1-microsecond bound on dependency waits makes the launch give up;
+    every workgroup leaves and the failure is reported, then a normal batch
+    still runs."""
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    tensors, hosts, probs = _problems([(sw.HEAT_F64, 128, 3000, 64, 31)])
+    announce("batch forced abort")
+    b = sw.Batch(probs, wait_limit_us=1)
+    b.run(stream)
+    rc = b.wait(stream)
+    assert rc == sw.SW_ERR_HIP and "time bound" in sw.last_error()
+    b.close()
+    tensors, hosts, probs = _problems([(sw.HEAT_F64, 128, 300, 64, 32)])
+    b = sw.Batch(probs)
+    b.run(stream)
+    assert b.wait(stream) == sw.SW_OK
+    alone = run(sw.HEAT_F64, hosts[0], 300, 0.25, 1.0, "swept", width=64)
+    assert np.array_equal(tensors[0].cpu().numpy(), alone)
+    b.close()
+
+
+def test_batch_rejects_bad_problems():
+    import torch
+    t = torch.zeros(1, 1024, dtype=torch.float64, device="cuda")
+    bad = [dict(eq=sw.HEAT_F64, width=48, n_cells=1024, n_steps=5, dt=0.25, dx=1.0,
+                d_state=t.data_ptr())]
+    with pytest.raises(sw.SweptError):
+        sw.Batch(bad)
+    bad[0]["width"] = 64
+    bad[0]["dt"] = -1.0
+    with pytest.raises(sw.SweptError):
+        sw.Batch(bad)
+
+
+# ---- autotuner -------------------------------------------------------------------
+
+def test_autotune_records_and_is_used():
+    sw.sw_tune_clear()
+    n = 1 << 16
+    announce("autotune heat_f64", n)
+    w, threads, ms = sw.sw_autotune(sw.HEAT_F64, n, 0)
+    assert w % 64 == 0 and n % w == 0 and n // w >= 2 and threads in (64, 128, 256) and ms > 0
+    assert sw.sw_tuned_width(sw.HEAT_F64, n) == (w, threads)
+    u0 = heat_ic(n, 41)
+    got = run(sw.HEAT_F64, pack(sw.HEAT_F64, u0), 333, 0.25, 1.0, "swept")[0]
+    assert np.array_equal(got, oracle.heat_f64(u0, 333, 0.25))
+    announce("autotune euler_f32")
+    w2, t2, _ = sw.sw_autotune(sw.EULER_F32, 4096, 8)
+    assert 4096 % w2 == 0
+    sw.sw_tune_clear()
+    assert sw.sw_tuned_width(sw.HEAT_F64, n) is None
+
+
+def test_autotune_cache_file_persists_across_processes():
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        env = dict(os.environ, SWEPT_TUNE_CACHE=path, PYTHONPATH=ROOT)
+        code_a = ("import paper_1811_08282_amd as sw; "
+                  "print(sw.sw_autotune(sw.HEAT_F64, 8192, 64)[:2])")
+        code_b = ("import paper_1811_08282_amd as sw; print(sw.sw_tuned_width(sw.HEAT_F64, 8192))")
+        announce("autotune cache file")
+        a = subprocess.run([sys.executable, "-c", code_a], env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert a.returncode == 0, a.stderr
+        b = subprocess.run([sys.executable, "-c", code_b], env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert b.returncode == 0, b.stderr
+        assert a.stdout.strip() == b.stdout.strip()
+        assert open(path).read().split()[0].startswith("gfx")
