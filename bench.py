@@ -47,8 +47,42 @@ WORKLOADS = {
 STRUCT_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 12, sw.EULER_F64: 56, sw.EULER_F32: 44}
 # algorithmic HBM bytes per cell-update of the classic path
 NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32: 140}
-# binary64 operations per cell-update (no fused multiply-add)
+# binary64 operations per heat cell-update: 3 subtractions/additions of the
+# difference form, one multiply by r, one add (no fused multiply-add)
 HEAT_FLOPS = 5
+# binary64 add/mul issue rate without FMA: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+FP64_NONFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = {
+    sw.HEAT_F64: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h"],
+    sw.HEAT_F32: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h"],
+    sw.EULER_F64: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h"],
+    sw.EULER_F32: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h"],
+}
+
+
+def kernel_source_hash(eq) -> str:
+    """sha256 of the sources of the swept phase kernel of `eq`."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[eq]:
+        with open(os.path.join(ROOT, "paper_1811_08282_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(work, eq, width):
+    """HBM bytes per phase launch measured with rocprofv3 counters (see
+    profiles/*_hbm_traffic.json), or None when absent or taken on other
+    kernel sources / another configuration."""
+    path = os.path.join(PROFILES, f"{work.name}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_hash(eq) or rec.get("width") != width:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def log(*a):
@@ -172,25 +206,24 @@ def main() -> int:
     naive_value = updates / (naive_ms * 1e-3) if naive_ms == naive_ms else None
     launch_ms = ms / phases
     tiles = work.n // width
-    # dominant kernel: the swept phase kernel (Diamond shape, all but 2 of the launches)
+    # dominant kernel: the swept phase kernel (all launches of a swept solve)
     alg_bytes = tiles * ((width + 2) + width) * STRUCT_BYTES[eq]
     achieved_gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
-    flops_per_launch = (HEAT_FLOPS if eq in (sw.HEAT_F64, sw.HEAT_F32) else None)
-    roofline = {
-        "bound": "hbm",
-        "achieved": achieved_gbs,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": achieved_gbs / HBM_PEAK_GBS,
-        "traffic": None,
-        "kernel": "swept phase kernel",
-        "launch_ms": launch_ms,
-        "algorithmic_bytes_per_launch": alg_bytes,
-    }
-    if flops_per_launch:
-        ops = value * flops_per_launch
-        roofline["fp64_ops_per_s"] = ops
-        roofline["fp64_nonfma_peak"] = FP64_VECTOR_TFLOPS / 2 * 1e12
+    hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes}
+    traffic = measured_traffic(work, eq, width)
+    if eq in (sw.HEAT_F64, sw.HEAT_F32):
+        # ALU-bound by design: the binary64 add/mul rate is the ceiling
+        achieved = value * HEAT_FLOPS / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_NONFMA_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / FP64_NONFMA_PEAK_TFLOPS,
+                    "traffic": traffic,
+                    "flops_per_launch": updates * HEAT_FLOPS / phases}
+    else:
+        roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic}
+    roofline.update({"kernel": "swept phase kernel", "launch_ms": launch_ms,
+                     "launches_per_step": phases, "hbm": hbm})
     out = {
         "metric": METRIC,
         "value": value,

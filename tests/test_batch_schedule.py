@@ -127,3 +127,22 @@ def test_dependency_rule():
     assert sw.sw_batch_item_deps(2, 7, 8) == [7, 0]
     assert sw.sw_batch_item_deps(3, 0, 8) == [7, 0]
     assert sw.sw_batch_item_deps(2, 1, 4, 1) == [0, 1, 2]
+
+
+def test_emulator_catches_a_weaker_rule(monkeypatch):
+    """Dropping either dependency must produce a detectable race."""
+    orig = sw.sw_batch_item_deps
+    rng = random.Random(1)
+    u0 = [rng.getrandbits(60) for _ in range(32)]
+    want = _naive(u0, 25)
+    for weaker in (lambda k, t, n, s=0: [], lambda k, t, n, s=0: orig(k, t, n, s)[:1],
+                   lambda k, t, n, s=0: orig(k, t, n, s)[1:]):
+        monkeypatch.setattr(sw, "sw_batch_item_deps", weaker)
+        caught = 0
+        for seed in range(10):
+            try:
+                caught += _emulate(u0, 25, 8, seed) != want
+            except (AssertionError, TypeError):
+                caught += 1
+        assert caught >= 5
+    monkeypatch.setattr(sw, "sw_batch_item_deps", orig)
