@@ -41,12 +41,16 @@ WORKLOADS = {
     "euler_f32_prec": (wl.EULER_PREC, sw.EULER_F32),
     "heat_f64_prec": (wl.HEAT_PREC, sw.HEAT_F64),
     "euler_f64_prec": (wl.EULER_PREC, sw.EULER_F64),
+    "euler_f64_flat_large": (wl.EULER_LARGE, sw.EULER_F64_FLAT),
+    "euler_f32_flat_prec": (wl.EULER_PREC, sw.EULER_F32_FLAT),
 }
 
 # algorithmic bytes of the swept working struct per cell (read + write per phase)
-STRUCT_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 12, sw.EULER_F64: 56, sw.EULER_F32: 44}
+STRUCT_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 12, sw.EULER_F64: 56, sw.EULER_F32: 44,
+                sw.EULER_F64_FLAT: 48, sw.EULER_F32_FLAT: 36}
 # algorithmic HBM bytes per cell-update of the classic path
-NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32: 140}
+NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32: 140,
+               sw.EULER_F64_FLAT: 120, sw.EULER_F32_FLAT: 84}
 # binary64 operations per heat cell-update: 3 subtractions/additions of the
 # difference form, one multiply by r, one add (no fused multiply-add)
 HEAT_FLOPS = 5
@@ -58,6 +62,8 @@ KERNEL_SOURCES = {
     sw.HEAT_F32: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h"],
     sw.EULER_F64: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h"],
     sw.EULER_F32: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h"],
+    sw.EULER_F64_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h"],
+    sw.EULER_F32_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h"],
 }
 
 
@@ -95,7 +101,7 @@ def pack_state(eq, q):
         return q.reshape(1, -1)
     if eq == sw.HEAT_F32:
         return np.stack([q.astype(np.float32), np.zeros(q.shape, np.float32)])
-    if eq == sw.EULER_F64:
+    if eq in (sw.EULER_F64, sw.EULER_F64_FLAT):
         return q
     return np.concatenate([q.astype(np.float32), np.zeros(q.shape, np.float32)])
 
@@ -188,9 +194,8 @@ def main() -> int:
     work, eq = WORKLOADS[args.workload]
     sw.load()
     width = args.width or sw.sw_default_width(eq, work.n)
-    s = 4 if eq in (sw.EULER_F64, sw.EULER_F32) else 1
-    final_level = work.steps * s
-    phases = sw.sw_phase_count(final_level, width)
+    final_level = work.steps * sw.substeps(eq)
+    phases = sw.sw_phase_count(final_level, width, sw.radius(eq))
     state0 = pack_state(eq, wl.initial_state(work))
     updates = work.n * work.steps
 
@@ -207,7 +212,7 @@ def main() -> int:
     launch_ms = ms / phases
     tiles = work.n // width
     # dominant kernel: the swept phase kernel (all launches of a swept solve)
-    alg_bytes = tiles * ((width + 2) + width) * STRUCT_BYTES[eq]
+    alg_bytes = tiles * ((width + 2 * sw.radius(eq)) + width) * STRUCT_BYTES[eq]
     achieved_gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
     hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes}
@@ -235,7 +240,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if eq in (sw.HEAT_F64, sw.EULER_F64) else "f32",
+        "dtype": "f64" if sw.is_f64(eq) else "f32",
         "data": "synthetic",
         "config": {"workload": work.name, "n_cells": work.n, "time_steps": work.steps,
                    "width": width, "method": "swept", "parallelism": "single-gpu"},

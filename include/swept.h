@@ -13,9 +13,14 @@
  *   heat  : u_t = u_xx, first order forward in time, central in space,
  *           r = dt / (dx * dx); one sub-step per time step.
  *   euler : 1D Euler equations, gamma = 1.4, second-order finite volume with
- *           a minmod limiter driven by a stored pressure ratio, predictor /
- *           corrector in time; lambda = dt / dx; four three-point sub-steps
- *           per time step: Pr(Q0), predictor, Pr(Q1), corrector.
+ *           a minmod limiter driven by a pressure ratio, predictor /
+ *           corrector in time; lambda = dt / dx.  Two layouts of the same
+ *           arithmetic (Sec. 4.3, Fig. 2): "lengthened" (SW_EULER_F64/F32),
+ *           four three-point sub-steps per time step -- Pr(Q0), predictor,
+ *           Pr(Q1), corrector -- on a struct of Q0, Q1, Pr; and "flattened"
+ *           (SW_EULER_*_FLAT), two five-point sub-steps -- predictor,
+ *           corrector, each recomputing the ratio -- on a struct of Q0, Q1.
+ *           Both leave bit-identical states after every time step.
  *
  * Precisions:
  *   *_F64 : binary64 throughout.
@@ -28,8 +33,9 @@
  * State layout (d_state, structure of arrays, n = n_cells, one allocation):
  *   SW_HEAT_F64  : double u[n]
  *   SW_HEAT_F32  : float  u[n], c[n]                  (c = Kahan compensation)
- *   SW_EULER_F64 : double rho[n], m[n], E[n]          (m = rho*u, E = total energy)
- *   SW_EULER_F32 : float  rho[n], m[n], E[n], c_rho[n], c_m[n], c_E[n]
+ *   SW_EULER_F64, SW_EULER_F64_FLAT : double rho[n], m[n], E[n]
+ *                                     (m = rho*u, E = total energy)
+ *   SW_EULER_F32, SW_EULER_F32_FLAT : float rho[n], m[n], E[n], c_rho[n], c_m[n], c_E[n]
  * The buffer is device memory of the current HIP device, at least
  * sw_state_bytes() long and 16-byte aligned.  It is read as the state at step
  * 0 and overwritten in place with the state at step n_steps.  Before the first
@@ -71,8 +77,10 @@ typedef enum {
 typedef enum {
     SW_HEAT_F64 = 0,
     SW_HEAT_F32 = 1,
-    SW_EULER_F64 = 2,
-    SW_EULER_F32 = 3
+    SW_EULER_F64 = 2,       /* lengthened layout: four 3-point sub-steps per step */
+    SW_EULER_F32 = 3,
+    SW_EULER_F64_FLAT = 4,  /* flattened layout: two 5-point sub-steps per step  */
+    SW_EULER_F32_FLAT = 5
 } sw_equation;
 
 typedef enum {
@@ -85,7 +93,8 @@ typedef void *sw_stream;
 
 /* Optional launch controls of swept_solve_ex / naive_solve_ex.
  *   width           : triangle width W in cells (swept only).  0 = library
- *                     choice.  Valid W: even, W >= 2, W divides n_cells,
+ *                     choice.  Valid W: a multiple of 2R (R = 2 for the
+ *                     flattened layout, else 1), W divides n_cells,
  *                     n_cells / W >= 2, W <= sw_max_width(eq).
  *   threads         : workgroup size of the swept phase kernels: 64, 128 or
  *                     256 (0 = library choice: W rounded up to a multiple of
@@ -107,8 +116,9 @@ size_t sw_state_bytes(int eq, int64_t n_cells);
 
 /* Bytes of working arrays a call needs: the swept method holds two copies of
  * the per-cell working struct (heat F64 16 B, heat F32 12 B, Euler F64 56 B,
- * Euler F32 44 B per cell); the naive method holds the second time level
- * (heat) or the predictor state and pressure ratio (Euler).  `width` is
+ * Euler F32 44 B, flattened Euler F64 48 B, F32 36 B per cell); the naive
+ * method holds the second time level (heat) or the predictor state (and, for
+ * the lengthened layout, the pressure ratio).  `width` is
  * unused by either method and may be 0.  0 for invalid arguments. */
 size_t sw_workspace_bytes(int eq, int64_t n_cells, int width, int method);
 
@@ -140,28 +150,30 @@ int naive_solve_ex(int eq, int64_t n_cells, int64_t n_steps, double dt, double d
 
 /* ---- schedule queries (host only, no HIP call) ------------------------
  * The swept schedule for a final sub-step level F (F = n_steps for heat,
- * 4 * n_steps for Euler) and width W = 2H has
+ * 4 * n_steps for lengthened Euler, 2 * n_steps for flattened Euler), width W
+ * and stencil radius R of one sub-step (1, or 2 for flattened Euler) has
+ * H = W / (2R) levels per half phase and
  *   K = 0 if F == 0, else ceil((F - 1) / H) + 1
  * phases.  Phase k (1-based) tiles the grid from cell offset
- * ((k - 1) % 2) * H in tiles of W cells; it lifts cell o of a tile
- * (o in [0, W), p(o) = min(o + 1, W - o)) from sub-step level
- * min(F, max(0, (k-1)H + 1 - p(o))) to min(F, (k-1)H + p(o)).  Phase 1 is the
- * Up Triangle, phase K the Down Triangle, the others Diamonds (the last ones
- * cut flat at F when F is not a multiple of H).                           */
+ * ((k - 1) % 2) * W/2 in tiles of W cells.  At level (k-1)H + j it computes
+ * the cells [R|j - 1|, W - R|j - 1|) of each tile, for j from 1 (k = 1) or
+ * 2 - H (k > 1) up to min(H, F - (k-1)H).  Phase 1 is the Up Triangle,
+ * phase K the Down Triangle, the others Diamonds (the last ones cut flat at
+ * F when F is not a multiple of H).                                       */
 
 /* Number of phases K; -1 for invalid arguments. */
-int64_t sw_phase_count(int64_t final_level, int width);
+int64_t sw_phase_count(int64_t final_level, int width, int radius);
 
 /* For phase k: the cell offset of its tiling and its first and last
  * sub-step level (first > last when the phase computes nothing).
  * SW_ERR_ARG for invalid arguments. */
-int sw_phase_info(int64_t k, int64_t final_level, int width, int64_t *offset,
+int sw_phase_info(int64_t k, int64_t final_level, int width, int radius, int64_t *offset,
                   int64_t *first_level, int64_t *last_level);
 
 /* Active cells of a tile of phase k at sub-step `level`: [*lo, *hi) in tile
  * coordinates (empty when *lo >= *hi).  SW_ERR_ARG for invalid arguments. */
-int sw_phase_interval(int64_t k, int64_t final_level, int width, int64_t level, int *lo,
-                      int *hi);
+int sw_phase_interval(int64_t k, int64_t final_level, int width, int radius, int64_t level,
+                      int *lo, int *hi);
 
 /* ---- autotuner ---------------------------------------------------------------
  * The paper recommends tuning the block width on a limited number of time

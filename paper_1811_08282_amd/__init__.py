@@ -18,10 +18,11 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswept.so")
 
-# equation x precision ids (sw_equation)
-HEAT_F64, HEAT_F32, EULER_F64, EULER_F32 = 0, 1, 2, 3
+# equation x precision x layout ids (sw_equation)
+HEAT_F64, HEAT_F32, EULER_F64, EULER_F32, EULER_F64_FLAT, EULER_F32_FLAT = 0, 1, 2, 3, 4, 5
 EQUATIONS = {"heat_f64": HEAT_F64, "heat_f32": HEAT_F32,
-             "euler_f64": EULER_F64, "euler_f32": EULER_F32}
+             "euler_f64": EULER_F64, "euler_f32": EULER_F32,
+             "euler_f64_flat": EULER_F64_FLAT, "euler_f32_flat": EULER_F32_FLAT}
 # methods (sw_method)
 METHOD_SWEPT, METHOD_NAIVE = 0, 1
 # status codes (sw_status)
@@ -80,12 +81,13 @@ def load() -> ctypes.CDLL:
     lib.sw_max_width.restype = i32
     lib.sw_default_width.argtypes = [i32, i64]
     lib.sw_default_width.restype = i32
-    lib.sw_phase_count.argtypes = [i64, i32]
+    lib.sw_phase_count.argtypes = [i64, i32, i32]
     lib.sw_phase_count.restype = i64
-    lib.sw_phase_info.argtypes = [i64, i64, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+    lib.sw_phase_info.argtypes = [i64, i64, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(i64)]
     lib.sw_phase_info.restype = i32
-    lib.sw_phase_interval.argtypes = [i64, i64, i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.sw_phase_interval.argtypes = [i64, i64, i32, i32, i64, ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32)]
     lib.sw_phase_interval.restype = i32
     lib.sw_last_error.argtypes = []
     lib.sw_last_error.restype = ctypes.c_char_p
@@ -170,22 +172,23 @@ def sw_default_width(eq, n_cells) -> int:
     return load().sw_default_width(eq, n_cells)
 
 
-def sw_phase_count(final_level, width) -> int:
-    return load().sw_phase_count(final_level, width)
+def sw_phase_count(final_level, width, radius=1) -> int:
+    return load().sw_phase_count(final_level, width, radius)
 
 
-def sw_phase_info(k, final_level, width):
+def sw_phase_info(k, final_level, width, radius=1):
     off, first, last = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    rc = load().sw_phase_info(k, final_level, width, ctypes.byref(off), ctypes.byref(first),
-                              ctypes.byref(last))
+    rc = load().sw_phase_info(k, final_level, width, radius, ctypes.byref(off),
+                              ctypes.byref(first), ctypes.byref(last))
     if rc:
         raise SweptError(rc, last_error())
     return off.value, first.value, last.value
 
 
-def sw_phase_interval(k, final_level, width, level):
+def sw_phase_interval(k, final_level, width, level, radius=1):
     lo, hi = ctypes.c_int(), ctypes.c_int()
-    rc = load().sw_phase_interval(k, final_level, width, level, ctypes.byref(lo), ctypes.byref(hi))
+    rc = load().sw_phase_interval(k, final_level, width, radius, level, ctypes.byref(lo),
+                                  ctypes.byref(hi))
     if rc:
         raise SweptError(rc, last_error())
     return lo.value, hi.value
@@ -285,17 +288,27 @@ def swept_solve_batch(problems, stream=None) -> int:
 # ---- torch convenience -----------------------------------------------------
 
 def substeps(eq: int) -> int:
-    return 4 if eq in (EULER_F64, EULER_F32) else 1
+    return {EULER_F64: 4, EULER_F32: 4, EULER_F64_FLAT: 2, EULER_F32_FLAT: 2}.get(eq, 1)
+
+
+def radius(eq: int) -> int:
+    """Stencil radius of one sub-step (2 for the flattened Euler layout)."""
+    return 2 if eq in (EULER_F64_FLAT, EULER_F32_FLAT) else 1
+
+
+def is_f64(eq: int) -> bool:
+    return eq in (HEAT_F64, EULER_F64, EULER_F64_FLAT)
 
 
 def state_dtype(eq: int):
     import torch
-    return torch.float64 if eq in (HEAT_F64, EULER_F64) else torch.float32
+    return torch.float64 if is_f64(eq) else torch.float32
 
 
 def state_rows(eq: int) -> int:
     """Arrays of n_cells in the state buffer (see include/swept.h)."""
-    return {HEAT_F64: 1, HEAT_F32: 2, EULER_F64: 3, EULER_F32: 6}[eq]
+    return {HEAT_F64: 1, HEAT_F32: 2, EULER_F64: 3, EULER_F32: 6,
+            EULER_F64_FLAT: 3, EULER_F32_FLAT: 6}[eq]
 
 
 def solve(eq: int, state, n_steps: int, dt: float, dx: float, method: str = "swept",

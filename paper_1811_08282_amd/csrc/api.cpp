@@ -40,9 +40,12 @@ int ok()
 
 const char *last_error() { return g_err.c_str(); }
 
-bool valid_eq(int eq) { return eq >= SW_HEAT_F64 && eq <= SW_EULER_F32; }
-bool is_euler(int eq) { return eq == SW_EULER_F64 || eq == SW_EULER_F32; }
-int substeps(int eq) { return is_euler(eq) ? 4 : 1; }
+bool valid_eq(int eq) { return eq >= SW_HEAT_F64 && eq <= SW_EULER_F32_FLAT; }
+bool is_euler(int eq) { return eq >= SW_EULER_F64; }
+bool is_flat(int eq) { return eq == SW_EULER_F64_FLAT || eq == SW_EULER_F32_FLAT; }
+bool is_f32(int eq) { return eq == SW_HEAT_F32 || eq == SW_EULER_F32 || eq == SW_EULER_F32_FLAT; }
+int substeps(int eq) { return is_flat(eq) ? 2 : (is_euler(eq) ? 4 : 1); }
+int radius(int eq) { return is_flat(eq) ? 2 : 1; }
 
 constexpr int64_t kMaxCells = (int64_t)1 << 40;
 constexpr int64_t kMaxWidth = 8192;
@@ -53,7 +56,9 @@ int lds_per_cell(int eq)
     case SW_HEAT_F64: return sw::kLdsPerCellHeatF64;
     case SW_HEAT_F32: return sw::kLdsPerCellHeatF32;
     case SW_EULER_F64: return sw::kLdsPerCellEulerF64;
-    default: return sw::kLdsPerCellEulerF32;
+    case SW_EULER_F32: return sw::kLdsPerCellEulerF32;
+    case SW_EULER_F64_FLAT: return sw::kLdsPerCellFlatF64;
+    default: return sw::kLdsPerCellFlatF32;
     }
 }
 
@@ -63,7 +68,9 @@ int struct_bytes(int eq)
     case SW_HEAT_F64: return sw::kStructBytesHeatF64;
     case SW_HEAT_F32: return sw::kStructBytesHeatF32;
     case SW_EULER_F64: return sw::kStructBytesEulerF64;
-    default: return sw::kStructBytesEulerF32;
+    case SW_EULER_F32: return sw::kStructBytesEulerF32;
+    case SW_EULER_F64_FLAT: return sw::kStructBytesFlatF64;
+    default: return sw::kStructBytesFlatF32;
     }
 }
 
@@ -74,15 +81,17 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int max_width(int eq)
 {
-    int64_t w = sw::kLdsBytes / lds_per_cell(eq) - 2;
+    const int step = 2 * radius(eq);
+    int64_t w = sw::kLdsBytes / lds_per_cell(eq) - 2 * radius(eq);
     if (w > kMaxWidth)
         w = kMaxWidth;
-    return (int)(w & ~(int64_t)1);
+    return (int)(w - w % step);
 }
 
 bool width_ok(int eq, int64_t n, int64_t w)
 {
-    return w >= 2 && (w % 2) == 0 && w <= max_width(eq) && (n % w) == 0 && n / w >= 2;
+    const int step = 2 * radius(eq);
+    return w >= step && (w % step) == 0 && w <= max_width(eq) && (n % w) == 0 && n / w >= 2;
 }
 
 int default_width(int eq, int64_t n)
@@ -98,8 +107,7 @@ size_t state_bytes(int eq, int64_t n)
     switch (eq) {
     case SW_HEAT_F64: return (size_t)n * 8;
     case SW_HEAT_F32: return (size_t)n * 8;
-    case SW_EULER_F64: return (size_t)n * 24;
-    default: return (size_t)n * 24;
+    default: return (size_t)n * 24;  // Euler, every precision and layout
     }
 }
 
@@ -112,7 +120,9 @@ size_t naive_ws_bytes(int eq, int64_t n)
     case SW_HEAT_F64: return round_up((size_t)n * 8, 256);
     case SW_HEAT_F32: return round_up((size_t)n * 4, 256);
     case SW_EULER_F64: return round_up((size_t)n * 24, 256) + round_up((size_t)n * 8, 256);
-    default: return round_up((size_t)n * 12, 256) + round_up((size_t)n * 8, 256);
+    case SW_EULER_F32: return round_up((size_t)n * 12, 256) + round_up((size_t)n * 8, 256);
+    case SW_EULER_F64_FLAT: return round_up((size_t)n * 24, 256);
+    default: return round_up((size_t)n * 12, 256);
     }
 }
 
@@ -239,7 +249,8 @@ int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
               hipStream_t s, int w, int threads, void *ws)
 {
     const int64_t final_level = steps * substeps(eq);
-    const int64_t half = w / 2;
+    const int rad = radius(eq);
+    const int64_t half = w / (2 * rad);
     const int64_t phases = sw::phase_count(final_level, half);
     const size_t copy = swept_copy_bytes(eq, n);
     char *ws_a = (char *)ws;
@@ -247,7 +258,7 @@ int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
     const double r64 = dt / (dx * dx);
     const double lam64 = dt / dx;
     for (int64_t k = 1; k <= phases; ++k) {
-        const sw::PhaseRange pr = sw::phase_range(k, final_level, half);
+        const sw::PhaseRange pr = sw::phase_range(k, final_level, half, rad);
         sw::PhaseLaunch p;
         p.n = n;
         p.w = w;
@@ -277,8 +288,16 @@ int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
             e = sw::euler_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out,
                                           lam64, s);
             break;
-        default:
+        case SW_EULER_F32:
             e = sw::euler_f32_swept_phase(p, (float *)state, in, out, (float)lam64, s);
+            break;
+        case SW_EULER_F64_FLAT:
+            e = sw::flat_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out,
+                                         lam64, s);
+            break;
+        default:
+            e = sw::flat_f32_swept_phase(p, (float *)state, (const float *)in, (float *)out,
+                                         (float)lam64, s);
             break;
         }
         if (e != hipSuccess)
@@ -332,6 +351,22 @@ int run_naive(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
             for (int sub = 0; sub < 4 && e == hipSuccess; ++sub)
                 e = sw::euler_f64_naive_substep(sub, q0, q1, pr, n, lam64, s);
         return launched(e, "naive euler launch");
+    }
+    if (eq == SW_EULER_F64_FLAT) {
+        double *q0 = (double *)state;
+        double *q1 = (double *)ws;
+        for (int64_t t = 0; t < steps && e == hipSuccess; ++t)
+            for (int sub = 0; sub < 2 && e == hipSuccess; ++sub)
+                e = sw::flat_f64_naive_substep(sub, q0, q1, n, lam64, s);
+        return launched(e, "naive flattened euler launch");
+    }
+    if (eq == SW_EULER_F32_FLAT) {
+        float *q0c = (float *)state;
+        float *q1 = (float *)ws;
+        for (int64_t t = 0; t < steps && e == hipSuccess; ++t)
+            for (int sub = 0; sub < 2 && e == hipSuccess; ++sub)
+                e = sw::flat_f32_naive_substep(sub, q0c, q1, n, (float)lam64, s);
+        return launched(e, "naive flattened euler launch");
     }
     float *q0c = (float *)state;
     float *q1 = (float *)ws;
@@ -445,39 +480,41 @@ int naive_solve_ex(int eq, int64_t n_cells, int64_t n_steps, double dt, double d
     return solve(SW_METHOD_NAIVE, eq, n_cells, n_steps, dt, dx, d_state, stream, opts);
 }
 
-int64_t sw_phase_count(int64_t final_level, int width)
+int64_t sw_phase_count(int64_t final_level, int width, int radius)
 {
-    if (final_level < 0 || width < 2 || (width & 1))
+    if (final_level < 0 || radius < 1 || radius > 2 || width < 2 * radius ||
+        width % (2 * radius) != 0)
         return -1;
-    return sw::phase_count(final_level, width / 2);
+    return sw::phase_count(final_level, width / (2 * radius));
 }
 
-int sw_phase_info(int64_t k, int64_t final_level, int width, int64_t *offset,
+int sw_phase_info(int64_t k, int64_t final_level, int width, int radius, int64_t *offset,
                   int64_t *first_level, int64_t *last_level)
 {
-    const int64_t phases = sw_phase_count(final_level, width);
+    const int64_t phases = sw_phase_count(final_level, width, radius);
     if (phases < 0 || k < 1 || k > phases || !offset || !first_level || !last_level)
         return fail(SW_ERR_ARG, "invalid phase query");
-    const sw::PhaseRange p = sw::phase_range(k, final_level, width / 2);
+    const sw::PhaseRange p = sw::phase_range(k, final_level, width / (2 * radius), radius);
     *offset = p.offset;
     *first_level = p.base + p.j_first;
     *last_level = p.base + p.j_last;
     return ok();
 }
 
-int sw_phase_interval(int64_t k, int64_t final_level, int width, int64_t level, int *lo, int *hi)
+int sw_phase_interval(int64_t k, int64_t final_level, int width, int radius, int64_t level,
+                      int *lo, int *hi)
 {
-    const int64_t phases = sw_phase_count(final_level, width);
+    const int64_t phases = sw_phase_count(final_level, width, radius);
     if (phases < 0 || k < 1 || k > phases || !lo || !hi)
         return fail(SW_ERR_ARG, "invalid phase query");
-    const sw::PhaseRange p = sw::phase_range(k, final_level, width / 2);
+    const sw::PhaseRange p = sw::phase_range(k, final_level, width / (2 * radius), radius);
     const int64_t j = level - p.base;
     if (j < p.j_first || j > p.j_last) {
         *lo = 0;
         *hi = 0;
         return ok();
     }
-    const int a = sw::window_margin((int)j);
+    const int a = sw::window_margin((int)j, radius);
     *lo = a;
     *hi = width - a;
     return ok();

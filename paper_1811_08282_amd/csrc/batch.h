@@ -8,7 +8,7 @@
 // body, then publishes its own flag.
 //
 // Dependencies of phase k > 1, tile t (tiles of phase k start at offset 0
-// for odd k and W/2 for even k):
+// for odd k and W/2 for even k; halos of R <= W/2 cells):
 //   k even: previous-phase tiles t and t+1;  k odd: t-1 and t   (mod tiles)
 // Those two tiles are the only previous-phase tiles that write cells this
 // tile reads (its W cells and both halos) and the only ones that read cells
@@ -40,6 +40,7 @@ struct BatchProblem {
     int eq;                // sw_equation
     int tiles;
     int single_phase;      // K == 1
+    int radius;            // stencil radius of one sub-step (2: flattened Euler)
 };
 
 struct BatchSegment {

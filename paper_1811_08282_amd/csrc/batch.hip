@@ -10,6 +10,7 @@
 #include "batch.h"
 #include "kernels.h"
 #include "tile_euler.h"
+#include "tile_flat.h"
 #include "tile_heat.h"
 
 namespace sw {
@@ -107,14 +108,14 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_persistent(BatchTables 
         if (P.single_phase && k == 2) {
             copy_out<kBatchThreads>(P, t);
         } else {
-            const int64_t half = P.w / 2;
-            const PhaseRange pr = phase_range(k, P.final_level, half);
+            const int64_t half = P.w / (2 * P.radius);
+            const PhaseRange pr = phase_range(k, P.final_level, half, P.radius);
             TileJob jb;
             jb.state = P.state;
             jb.ws_in = (k % 2 == 0) ? P.ws0 : P.ws1;
             jb.ws_out = (k % 2 == 1) ? P.ws0 : P.ws1;
             jb.n = P.n;
-            jb.g0 = pr.offset + (int64_t)t * P.w - 1;
+            jb.g0 = pr.offset + (int64_t)t * P.w - P.radius;
             jb.base = pr.base;
             jb.coef = P.coef;
             jb.w = P.w;
@@ -126,7 +127,9 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_persistent(BatchTables 
             case 0: heat_f64_tile<kBatchThreads>(jb, lds); break;
             case 1: heat_f32_tile<kBatchThreads>(jb, (float *)lds); break;
             case 2: euler_f64_tile<kBatchThreads>(jb, lds); break;
-            default: euler_f32_tile<kBatchThreads>(jb, lds); break;
+            case 3: euler_f32_tile<kBatchThreads>(jb, lds); break;
+            case 4: flat_f64_tile<kBatchThreads>(jb, lds); break;
+            default: flat_f32_tile<kBatchThreads>(jb, lds); break;
             }
         }
         // publish: every thread's stores reach device scope before the flag

@@ -1,0 +1,169 @@
+// euler_flat.hip -- kernels of the flattened Euler layout (Sec. 4.3,
+// Fig. 2a): the swept phase kernel (body in tile_flat.h) and the classic
+// kernel, one launch per five-point sub-step (two per time step).
+#include "kernels.h"
+#include "tile_flat.h"
+
+namespace sw {
+namespace {
+
+constexpr int kNaiveBlock = 256;
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_flat_f64_phase(double *__restrict__ state, const double *__restrict__ ws_in,
+                 double *__restrict__ ws_out, int64_t n, int w, int64_t offset, int64_t base,
+                 int j_first, int j_last, double lam, int first, int last)
+{
+    extern __shared__ double lds[];
+    TileJob jb{state, ws_in, ws_out, n, offset + (int64_t)blockIdx.x * w - kFlatRadius, base, lam,
+               w, j_first, j_last, first, last};
+    flat_f64_tile<NT>(jb, lds);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_flat_f32_phase(float *__restrict__ state, const float *__restrict__ ws_in,
+                 float *__restrict__ ws_out, int64_t n, int w, int64_t offset, int64_t base,
+                 int j_first, int j_last, float lam, int first, int last)
+{
+    extern __shared__ double ldsd[];
+    TileJob jb{state, ws_in, ws_out, n, offset + (int64_t)blockIdx.x * w - kFlatRadius, base,
+               (double)lam, w, j_first, j_last, first, last};
+    flat_f32_tile<NT>(jb, ldsd);
+}
+
+// Classic flattened sub-step: t = 0 predictor (q1 from q0), t = 1 corrector
+// (q0 += ... from q1).  Block-local pressures, ratios and face fluxes.
+__global__ void __launch_bounds__(kNaiveBlock)
+k_flat_f64_naive(int t, double *__restrict__ q0, double *__restrict__ q1, int64_t n, double lam)
+{
+    __shared__ double p[kNaiveBlock + 4];
+    __shared__ double pr[kNaiveBlock + 2];
+    __shared__ double f[3][kNaiveBlock + 1];
+    const int64_t b0 = (int64_t)blockIdx.x * kNaiveBlock;
+    const int nloc = (int)((n - b0) < kNaiveBlock ? (n - b0) : kNaiveBlock);
+    const double *q = (t == 0) ? q0 : q1;
+    for (int i = threadIdx.x; i < nloc + 4; i += blockDim.x) {  // cells b0-2 .. b0+nloc+1
+        const int64_t g = wrap_cell(b0 - 2 + i, n);
+        p[i] = pressure64(q[g], q[n + g], q[2 * n + g]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc + 2; i += blockDim.x)    // cells b0-1 .. b0+nloc
+        pr[i] = ratio(p[i], p[i + 1], p[i + 2]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc + 1; i += blockDim.x) {  // faces (b0-1+i | b0+i)
+        const int64_t gl = wrap_cell(b0 - 1 + i, n);
+        const int64_t gr = wrap_cell(b0 + i, n);
+        face64(q[gl], q[n + gl], q[2 * n + gl], q[gr], q[n + gr], q[2 * n + gr], pr[i], pr[i + 1],
+               f[0][i], f[1][i], f[2][i]);
+    }
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i >= nloc)
+        return;
+    const int64_t g = b0 + i;
+    if (t == 0) {
+        const double hl = 0.5 * lam;
+        for (int k = 0; k < 3; ++k)
+            q1[k * n + g] = q0[k * n + g] + hl * (f[k][i] - f[k][i + 1]);
+    } else {
+        for (int k = 0; k < 3; ++k)
+            q0[k * n + g] = q0[k * n + g] + lam * (f[k][i] - f[k][i + 1]);
+    }
+}
+
+// q0c: caller state (q0[3][n] then c[3][n])
+__global__ void __launch_bounds__(kNaiveBlock)
+k_flat_f32_naive(int t, float *__restrict__ q0c, float *__restrict__ q1, int64_t n, float lam)
+{
+    __shared__ double p[kNaiveBlock + 4];
+    __shared__ double pr[kNaiveBlock + 2];
+    __shared__ float f[3][kNaiveBlock + 1];
+    const int64_t b0 = (int64_t)blockIdx.x * kNaiveBlock;
+    const int nloc = (int)((n - b0) < kNaiveBlock ? (n - b0) : kNaiveBlock);
+    const float *q = (t == 0) ? q0c : q1;
+    for (int i = threadIdx.x; i < nloc + 4; i += blockDim.x) {
+        const int64_t g = wrap_cell(b0 - 2 + i, n);
+        p[i] = pressure32(q[g], q[n + g], q[2 * n + g]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc + 2; i += blockDim.x)
+        pr[i] = ratio(p[i], p[i + 1], p[i + 2]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc + 1; i += blockDim.x) {
+        const int64_t gl = wrap_cell(b0 - 1 + i, n);
+        const int64_t gr = wrap_cell(b0 + i, n);
+        face32(q[gl], q[n + gl], q[2 * n + gl], q[gr], q[n + gr], q[2 * n + gr], pr[i], pr[i + 1],
+               f[0][i], f[1][i], f[2][i]);
+    }
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i >= nloc)
+        return;
+    const int64_t g = b0 + i;
+    if (t == 0) {
+        const float hl = 0.5f * lam;
+        for (int k = 0; k < 3; ++k)
+            q1[k * n + g] = q0c[k * n + g] + hl * (f[k][i] - f[k][i + 1]);
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            float c = q0c[(3 + k) * n + g];
+            q0c[k * n + g] = kahan_add(q0c[k * n + g], lam * (f[k][i] - f[k][i + 1]), c);
+            q0c[(3 + k) * n + g] = c;
+        }
+    }
+}
+
+template <typename K64, typename K128, typename K256, typename... Args>
+hipError_t launch_by_threads(int nt, K64 k64, K128 k128, K256 k256, dim3 grid, size_t lds,
+                             hipStream_t s, Args... args)
+{
+    if (nt == 64)
+        hipLaunchKernelGGL(k64, grid, dim3(64), lds, s, args...);
+    else if (nt == 128)
+        hipLaunchKernelGGL(k128, grid, dim3(128), lds, s, args...);
+    else
+        hipLaunchKernelGGL(k256, grid, dim3(256), lds, s, args...);
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t flat_f64_swept_phase(const PhaseLaunch &p, double *state, const double *ws_in,
+                                double *ws_out, double lam, hipStream_t s)
+{
+    const size_t lds = (size_t)(p.w + 2 * kFlatRadius) * kLdsPerCellFlatF64;
+    return launch_by_threads(p.threads, k_flat_f64_phase<64>, k_flat_f64_phase<128>,
+                             k_flat_f64_phase<256>, dim3((unsigned)(p.n / p.w)), lds, s, state,
+                             ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+                             (int)p.first, (int)p.last);
+}
+
+hipError_t flat_f32_swept_phase(const PhaseLaunch &p, float *state, const float *ws_in,
+                                float *ws_out, float lam, hipStream_t s)
+{
+    const size_t lds = (size_t)(p.w + 2 * kFlatRadius) * kLdsPerCellFlatF32;
+    return launch_by_threads(p.threads, k_flat_f32_phase<64>, k_flat_f32_phase<128>,
+                             k_flat_f32_phase<256>, dim3((unsigned)(p.n / p.w)), lds, s, state,
+                             ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+                             (int)p.first, (int)p.last);
+}
+
+hipError_t flat_f64_naive_substep(int t, double *q0, double *q1, int64_t n, double lam,
+                                  hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((n + kNaiveBlock - 1) / kNaiveBlock);
+    hipLaunchKernelGGL(k_flat_f64_naive, dim3(blocks), dim3(kNaiveBlock), 0, s, t, q0, q1, n, lam);
+    return hipGetLastError();
+}
+
+hipError_t flat_f32_naive_substep(int t, float *q0c, float *q1, int64_t n, float lam,
+                                  hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((n + kNaiveBlock - 1) / kNaiveBlock);
+    hipLaunchKernelGGL(k_flat_f32_naive, dim3(blocks), dim3(kNaiveBlock), 0, s, t, q0c, q1, n, lam);
+    return hipGetLastError();
+}
+
+} // namespace sw

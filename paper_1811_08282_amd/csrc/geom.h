@@ -1,6 +1,12 @@
 // geom.h -- geometry of the swept schedule, shared by the host planner and
 // the phase kernels.
 //
+// Written here for a three-point stencil (radius R = 1).  A sub-step of
+// radius R (the five-point "flattened" Euler sub-steps have R = 2) scales
+// every margin by R: H = W / (2R) levels per half phase, windows
+// [R|j - 1|, W - R|j - 1|), R halo cells per side; the tiling still shifts by
+// W/2 between phases.
+//
 // Sub-step levels: level 0 is the initial state, level m the state after m
 // sub-steps; the run ends at level F.  With tile width W = 2H the schedule
 // has K phases (Sec. 4.1): phase 1 is the Up Triangle, phases 2..K-1 the
@@ -49,11 +55,12 @@ struct PhaseRange {
     int j_last;      // last relative level (j_first > j_last: nothing to do)
 };
 
-SW_HD PhaseRange phase_range(int64_t k, int64_t final_level, int64_t half)
+// `half` = H, levels per half phase (W / 2R); `radius` = R
+SW_HD PhaseRange phase_range(int64_t k, int64_t final_level, int64_t half, int radius = 1)
 {
     PhaseRange p;
     p.base = (k - 1) * half;
-    p.offset = ((k - 1) & 1) ? half : 0;
+    p.offset = ((k - 1) & 1) ? half * radius : 0;
     p.j_first = (k == 1) ? 1 : (int)(2 - half);
     int64_t top = final_level - p.base;
     p.j_last = (int)(top < half ? top : half);
@@ -61,9 +68,9 @@ SW_HD PhaseRange phase_range(int64_t k, int64_t final_level, int64_t half)
 }
 
 // distance of the active window from each tile edge at relative level j
-SW_HD int window_margin(int j)
+SW_HD int window_margin(int j, int radius = 1)
 {
-    return j >= 1 ? j - 1 : 1 - j;
+    return radius * (j >= 1 ? j - 1 : 1 - j);
 }
 
 } // namespace sw

@@ -17,7 +17,10 @@ const char *last_error();
 
 bool valid_eq(int eq);
 bool is_euler(int eq);
+bool is_flat(int eq);
+bool is_f32(int eq);
 int substeps(int eq);
+int radius(int eq);
 int lds_per_cell(int eq);
 int struct_bytes(int eq);
 int preferred_width(int eq);

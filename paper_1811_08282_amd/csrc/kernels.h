@@ -16,12 +16,16 @@ constexpr int kStructBytesHeatF64 = 16;   // u at even / odd levels
 constexpr int kStructBytesHeatF32 = 12;   // u even / odd, Kahan c
 constexpr int kStructBytesEulerF64 = 56;  // Q0[3], Q1[3], Pr
 constexpr int kStructBytesEulerF32 = 44;  // Q0[3], c[3], Q1[3] (f32), Pr (f64)
+constexpr int kStructBytesFlatF64 = 48;   // Q0[3], Q1[3]
+constexpr int kStructBytesFlatF32 = 36;   // Q0[3], c[3], Q1[3] (f32)
 
 // LDS bytes per tile cell of each swept kernel (struct + scratch).
 constexpr int kLdsPerCellHeatF64 = 16;
 constexpr int kLdsPerCellHeatF32 = 12;
 constexpr int kLdsPerCellEulerF64 = 80;  // struct 56 + face flux / pressure 24
 constexpr int kLdsPerCellEulerF32 = 56;  // struct 44 + face flux / pressure 12
+constexpr int kLdsPerCellFlatF64 = 88;   // struct 48 + pressure, ratio 16 + face flux 24
+constexpr int kLdsPerCellFlatF32 = 64;   // struct 36 + pressure, ratio 16 + face flux 12
 
 // Description of one swept phase launch.
 struct PhaseLaunch {
@@ -67,5 +71,17 @@ hipError_t euler_f32_swept_phase(const PhaseLaunch &p, float *state, const void 
                                  void *ws_out, float lam, hipStream_t s);
 hipError_t euler_f32_naive_substep(int t, float *q0c, float *q1, double *pr, int64_t n,
                                    float lam, hipStream_t s);
+
+// Euler, flattened layout (two five-point sub-steps per step), binary64:
+// ws: Q0[3][n], Q1[3][n]; classic sub-step t = 0 predictor, 1 corrector.
+hipError_t flat_f64_swept_phase(const PhaseLaunch &p, double *state, const double *ws_in,
+                                double *ws_out, double lam, hipStream_t s);
+hipError_t flat_f64_naive_substep(int t, double *q0, double *q1, int64_t n, double lam,
+                                  hipStream_t s);
+// binary32: ws: q0[3][n], c[3][n], q1[3][n] floats; classic q0c = caller state.
+hipError_t flat_f32_swept_phase(const PhaseLaunch &p, float *state, const float *ws_in,
+                                float *ws_out, float lam, hipStream_t s);
+hipError_t flat_f32_naive_substep(int t, float *q0c, float *q1, int64_t n, float lam,
+                                  hipStream_t s);
 
 } // namespace sw

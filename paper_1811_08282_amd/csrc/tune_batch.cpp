@@ -156,6 +156,7 @@ hipError_t fill_state(int eq, void *state, int64_t n, hipStream_t s)
             e = fill_f32((float *)state + n, n, 0.0f, s);
         break;
     case SW_EULER_F64:
+    case SW_EULER_F64_FLAT:
         e = fill_f64((double *)state, n, 1.0, s);
         if (e == hipSuccess)
             e = fill_f64((double *)state + n, n, 0.0, s);
@@ -401,15 +402,16 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
         b.eq = p.eq;
         b.tiles = (int)(p.n_cells / w);
         b.final_level = p.n_steps * substeps(p.eq);
-        b.phases = sw::phase_count(b.final_level, w / 2);
+        b.radius = radius(p.eq);
+        b.phases = sw::phase_count(b.final_level, w / (2 * b.radius));
         b.single_phase = (b.phases == 1);
         b.coef = is_euler(p.eq) ? p.dt / p.dx : p.dt / (p.dx * p.dx);
-        if (p.eq == SW_HEAT_F32 || p.eq == SW_EULER_F32)
+        if (is_f32(p.eq))
             b.coef = (double)(float)b.coef;
         b.flag_off = flags;
         flags += b.tiles;
         array_bytes += 2 * swept_copy_bytes(p.eq, p.n_cells);
-        max_lds = std::max(max_lds, (size_t)(w + 2) * (size_t)lds_per_cell(p.eq));
+        max_lds = std::max(max_lds, (size_t)(w + 2 * b.radius) * (size_t)lds_per_cell(p.eq));
         max_phase = std::max<int64_t>(max_phase, b.phases + (b.single_phase ? 1 : 0));
     }
     // segments, phase-major

@@ -1,4 +1,6 @@
 """Helpers shared by the GPU tests: device round trips through the C ABI."""
+import json
+import os
 import sys
 
 import numpy as np
@@ -42,3 +44,15 @@ def rel_inf(a, b):
     b = np.asarray(b, np.float64)
     den = np.max(np.abs(b))
     return float(np.max(np.abs(a - b)) / den) if den else float(np.max(np.abs(a - b)))
+
+
+def record(name, **values):
+    """Append a measured figure (e.g. an error against the oracle) to
+    gpurun_out/measured.jsonl when that folder exists, and print it."""
+    line = json.dumps(dict(name=name, **values))
+    print("[measured]", line, flush=True)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = os.path.join(root, "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "measured.jsonl"), "a") as f:
+            f.write(line + "\n")

@@ -37,22 +37,33 @@ def test_state_and_workspace_sizes():
     assert sw.sw_state_bytes(sw.EULER_F64, n) == 24 * n
     assert sw.sw_state_bytes(sw.EULER_F32, n) == 24 * n
     assert sw.sw_state_bytes(7, n) == 0
-    for eq, per_cell in ((sw.HEAT_F64, 16), (sw.HEAT_F32, 12), (sw.EULER_F64, 56), (sw.EULER_F32, 44)):
+    assert sw.sw_state_bytes(sw.EULER_F64_FLAT, n) == 24 * n
+    assert sw.sw_state_bytes(sw.EULER_F32_FLAT, n) == 24 * n
+    for eq, per_cell in ((sw.HEAT_F64, 16), (sw.HEAT_F32, 12), (sw.EULER_F64, 56), (sw.EULER_F32, 44),
+                         (sw.EULER_F64_FLAT, 48), (sw.EULER_F32_FLAT, 36)):
         assert sw.sw_workspace_bytes(eq, n, 0, sw.METHOD_SWEPT) == 2 * per_cell * n
+    assert sw.sw_workspace_bytes(sw.EULER_F64_FLAT, n, 0, sw.METHOD_NAIVE) == 24 * n
     assert sw.sw_workspace_bytes(sw.HEAT_F64, n, 0, sw.METHOD_NAIVE) == 8 * n
     assert sw.sw_workspace_bytes(sw.EULER_F64, n, 0, sw.METHOD_NAIVE) == 32 * n
     assert sw.sw_workspace_bytes(sw.EULER_F64, n, 0, 9) == 0
 
 
 def test_width_limits():
-    for eq, per_cell in ((sw.HEAT_F64, 16), (sw.HEAT_F32, 12), (sw.EULER_F64, 80), (sw.EULER_F32, 56)):
+    for eq, per_cell, rad in ((sw.HEAT_F64, 16, 1), (sw.HEAT_F32, 12, 1), (sw.EULER_F64, 80, 1),
+                              (sw.EULER_F32, 56, 1), (sw.EULER_F64_FLAT, 88, 2),
+                              (sw.EULER_F32_FLAT, 64, 2)):
         wmax = sw.sw_max_width(eq)
-        assert wmax % 2 == 0 and (wmax + 2) * per_cell <= 160 * 1024 and wmax <= 8192
+        assert wmax % (2 * rad) == 0 and (wmax + 2 * rad) * per_cell <= 160 * 1024
+        assert wmax <= 8192
     assert sw.sw_default_width(sw.HEAT_F64, 1 << 22) == 1024
     assert sw.sw_default_width(sw.EULER_F64, 1 << 22) == 256
     assert sw.sw_default_width(sw.HEAT_F64, 1000) == 500  # largest even divisor with n/W >= 2
     assert sw.sw_default_width(sw.HEAT_F64, 1001) == 0    # odd: no even divisor
     assert sw.sw_default_width(sw.HEAT_F64, 6) == 2
+    # flattened Euler needs widths that are multiples of 4
+    assert sw.sw_default_width(sw.EULER_F64_FLAT, 1 << 22) == 256
+    assert sw.sw_default_width(sw.EULER_F64_FLAT, 24) == 12
+    assert sw.sw_default_width(sw.EULER_F64_FLAT, 18) == 0
 
 
 FAKE = 0x1000  # never dereferenced: every case below fails or returns before any HIP call
@@ -83,6 +94,12 @@ def test_invalid_width_rejected_on_host(width):
     # n = 1024: 6 does not divide it, 1024 leaves one tile, 100000 is too wide
     rc = sw.swept_solve_ex(sw.HEAT_F64, 1024, 5, 0.25, 1.0, FAKE, None, width=width)
     assert rc == sw.SW_ERR_ARG, sw.last_error()
+
+
+def test_flat_width_must_be_multiple_of_four():
+    rc = sw.swept_solve_ex(sw.EULER_F64_FLAT, 1024, 5, 0.1, 1.0, FAKE, None, width=34)
+    assert rc == sw.SW_ERR_ARG
+    assert sw.swept_solve(sw.EULER_F32_FLAT, 1026, 5, 0.1, 1.0, FAKE, None) == sw.SW_ERR_UNSUPPORTED
 
 
 def test_no_valid_width_is_unsupported():

@@ -28,6 +28,11 @@ def _ic(eq, n, seed):
     return sod_tiled(n, n)
 
 
+def _pack_eq(eq):
+    """state layout of the flattened ids equals the lengthened ones"""
+    return {sw.EULER_F64_FLAT: sw.EULER_F64, sw.EULER_F32_FLAT: sw.EULER_F32}.get(eq, eq)
+
+
 def _coef(eq):
     return (0.25, 1.0) if eq in (sw.HEAT_F64, sw.HEAT_F32) else (0.1, 1.0)
 
@@ -37,7 +42,7 @@ def _problems(specs):
     import torch
     tensors, hosts, probs = [], [], []
     for eq, n, steps, width, seed in specs:
-        host = pack(eq, _ic(eq, n, seed))
+        host = pack(_pack_eq(eq), _ic(eq, n, seed))
         t = torch.from_numpy(np.ascontiguousarray(host)).cuda()
         dt, dx = _coef(eq)
         tensors.append(t)
@@ -57,6 +62,8 @@ MIXED = [
     (sw.HEAT_F64, 1000, 77, 40, 6),      # ragged width
     (sw.EULER_F64, 512, 9, 2, 7),        # width 2: one level per phase
     (sw.HEAT_F32, 8192, 333, 1024, 8),
+    (sw.EULER_F64_FLAT, 2048, 41, 128, 9),   # flattened layout, radius-2 halos
+    (sw.EULER_F32_FLAT, 1024, 17, 4, 10),
 ]
 
 
@@ -77,7 +84,7 @@ def test_mixed_batch_equals_individual_swept_and_oracle():
         assert np.array_equal(got, alone), (eq, n, steps, width)
         if eq == sw.HEAT_F64:
             assert np.array_equal(got[0], oracle.heat_f64(host[0], steps, dt / dx ** 2))
-        elif eq == sw.EULER_F64:
+        elif eq in (sw.EULER_F64, sw.EULER_F64_FLAT):
             assert np.array_equal(got, oracle.euler_f64(host, steps, dt / dx))
         elif eq == sw.HEAT_F32:
             u, c = oracle.heat_f32(host[0], host[1], steps, dt / dx ** 2)

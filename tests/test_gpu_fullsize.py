@@ -20,7 +20,7 @@ import pytest
 import oracle
 import paper_1811_08282_amd as sw
 from paper_1811_08282_amd import workloads as wl
-from gpu_util import announce, pack, rel_inf, run
+from gpu_util import announce, pack, record, rel_inf, run
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +66,22 @@ def test_euler_f64_n4194304_10000_steps():
     assert np.array_equal(swept, naive)
     tile = oracle.euler_f64(q0[:, :w.tile], w.steps, w.dt / w.dx)
     tiles = swept.reshape(3, w.n // w.tile, w.tile)
+    record("euler_f64_n4194304_s10000_vs_oracle",
+           max_abs_diff=float(np.max(np.abs(tiles - tile[:, None, :]))))
+    assert np.array_equal(tiles, np.broadcast_to(tile[:, None, :], tiles.shape))
+
+
+def test_euler_f64_flat_n4194304_10000_steps():
+    """The flattened layout at full size equals the oracle tile bit for bit."""
+    w = wl.EULER_LARGE
+    q0 = wl.initial_state(w)
+    announce("fullsize euler_f64_flat swept", w.n, w.steps)
+    swept = run(sw.EULER_F64_FLAT, pack(sw.EULER_F64, q0), w.steps, w.dt, w.dx, "swept")
+    announce("fullsize euler_f64_flat naive")
+    naive = run(sw.EULER_F64_FLAT, pack(sw.EULER_F64, q0), w.steps, w.dt, w.dx, "naive")
+    assert np.array_equal(swept, naive)
+    tile = oracle.euler_f64(q0[:, :w.tile], w.steps, w.dt / w.dx)
+    tiles = swept.reshape(3, w.n // w.tile, w.tile)
     assert np.array_equal(tiles, np.broadcast_to(tile[:, None, :], tiles.shape))
 
 
@@ -92,7 +108,9 @@ def test_heat_f32_n16777216_20000_steps_error_vs_f64():
     ref = _heat_cone_samples(u32.astype(np.float64), w.steps, r, starts, span, oracle.heat_f64)
     got = np.concatenate([swept[0][(np.arange(s, s + span)) % w.n] for s in starts])
     want = np.concatenate([ref[s] for s in starts])
-    assert rel_inf(got, want) < 1e-6
+    err = rel_inf(got, want)
+    record("heat_f32_n16777216_s20000_vs_f64", rel_inf=err, cells=int(got.size))
+    assert err < 1e-6
 
 
 def test_euler_f32_n16777216_20000_steps_error_vs_f64():
@@ -112,8 +130,8 @@ def test_euler_f32_n16777216_20000_steps_error_vs_f64():
     # dominates: rel_1 of rho and E, the smooth-norm measures, are gated)
     ref = oracle.euler_f64(q32.astype(np.float64), w.steps, w.dt / w.dx)
     rel1 = np.abs(tq - ref).sum(axis=1) / np.abs(ref).sum(axis=1)
-    print("[euler_f32 vs f64] rel_1 rho, m, E =", rel1.tolist(),
-          " rel_inf =", [rel_inf(tq[k], ref[k]) for k in range(3)])
+    record("euler_f32_n16777216_s20000_vs_f64", rel_1=rel1.tolist(),
+           rel_inf=[rel_inf(tq[k], ref[k]) for k in range(3)])
     assert rel1[0] < 1e-2 and rel1[2] < 1e-2
 
 

@@ -183,3 +183,49 @@ def test_euler_f32_matches_f32_oracle_bitexact(width):
     ref64 = oracle.euler_f64(q32.astype(np.float64), steps, 0.1)
     rel1 = np.abs(swp[:3] - ref64).sum(axis=1) / np.abs(ref64).sum(axis=1)
     assert rel1[0] < 1e-3 and rel1[2] < 1e-3
+
+
+# ---- Euler, flattened layout (two five-point sub-steps per step) ------------------
+
+@pytest.mark.parametrize("width", [4, 8, 64, 256, 1024])
+def test_euler_flat_f64_equals_lengthened_and_oracle(width):
+    n = 2048
+    q0 = sod_tiled(n, 512)
+    q0[1] += 0.05 * q0[0]
+    rng = np.random.default_rng(100 + width)
+    for steps in sorted({1, 2, max(1, width // 4), int(rng.integers(1, 300))}):
+        want = oracle.euler_f64(q0, steps, 0.1)
+        announce("euler_f64_flat swept W", width, "steps", steps)
+        got = run(sw.EULER_F64_FLAT, pack(sw.EULER_F64, q0), steps, 0.1, 1.0, "swept", width=width)
+        assert np.array_equal(got, want), (width, steps, rel_inf(got, want))
+    announce("euler_f64_flat naive")
+    naive = run(sw.EULER_F64_FLAT, pack(sw.EULER_F64, q0), steps, 0.1, 1.0, "naive")
+    assert np.array_equal(naive, want)
+
+
+def test_euler_flat_f64_ragged_chunked_shift():
+    n, w = 1000, 40
+    q0 = _smooth_euler(n, 3)
+    announce("euler_f64_flat ragged")
+    one = run(sw.EULER_F64_FLAT, pack(sw.EULER_F64, q0), 111, 0.1, 1.0, "swept", width=w)
+    assert np.array_equal(one, oracle.euler_f64(q0, 111, 0.1))
+    parts = run(sw.EULER_F64_FLAT, pack(sw.EULER_F64, q0), 111, 0.1, 1.0, "swept", width=w,
+                chunks=[1, 10, 100])
+    assert np.array_equal(parts, one)
+    sh = run(sw.EULER_F64_FLAT, pack(sw.EULER_F64, np.roll(q0, 13, axis=1)), 111, 0.1, 1.0,
+             "swept", width=w)
+    assert np.array_equal(sh, np.roll(one, 13, axis=1))
+
+
+@pytest.mark.parametrize("width", [4, 64, 512])
+def test_euler_flat_f32_matches_f32_oracle_bitexact(width):
+    n, steps = 2048, 300
+    q0 = sod_tiled(n, 1024)
+    q32 = q0.astype(np.float32)
+    want_q, want_c = oracle.euler_f32(q32, np.zeros_like(q32), steps, 0.1)
+    announce("euler_f32_flat swept W", width)
+    swp = run(sw.EULER_F32_FLAT, pack(sw.EULER_F32, q0), steps, 0.1, 1.0, "swept", width=width)
+    announce("euler_f32_flat naive")
+    nv = run(sw.EULER_F32_FLAT, pack(sw.EULER_F32, q0), steps, 0.1, 1.0, "naive")
+    assert np.array_equal(nv[:3], want_q) and np.array_equal(nv[3:], want_c)
+    assert np.array_equal(swp, nv)

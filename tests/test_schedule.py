@@ -31,10 +31,10 @@ def _h(*xs):
     return v
 
 
-def _phases(final_level, width):
-    k_count = sw.sw_phase_count(final_level, width)
+def _phases(final_level, width, radius=1):
+    k_count = sw.sw_phase_count(final_level, width, radius)
     for k in range(1, k_count + 1):
-        off, first, last = sw.sw_phase_info(k, final_level, width)
+        off, first, last = sw.sw_phase_info(k, final_level, width, radius)
         yield k, k_count, off, first, last
 
 
@@ -175,3 +175,111 @@ def test_phase_counts_match_the_paper_structure():
         lo, hi = sw.sw_phase_interval(3, levels, w, m)
         total += hi - lo
     assert off == 0 and total == w * w // 2
+
+
+# ---- radius 2 (the flattened Euler layout): five-point sub-steps ---------------
+
+def _naive_r2(u0, levels):
+    n = len(u0)
+    u = list(u0)
+    for m in range(1, levels + 1):
+        u = [_h(u[i - 2], u[i - 1], u[i], u[(i + 1) % n], u[(i + 2) % n], m) for i in range(n)]
+    return u
+
+
+def _swept_r2(u0, levels, width):
+    """Two-slot struct, halos of two cells, margins doubled."""
+    n, R = len(u0), 2
+    cur = [(v, None, 0) for v in u0]
+    computed = set()
+    for k, k_count, off, first, last in _phases(levels, width, R):
+        nxt = [None] * n
+        for t0 in range(off, off + n, width):
+            idx = [(t0 - R + i) % n for i in range(width + 2 * R)]
+            s = [[cur[g][0], cur[g][1]] for g in idx]
+            top = [cur[g][2] for g in idx]
+            for m in range(first, last + 1):
+                lo, hi = sw.sw_phase_interval(k, levels, width, m, R)
+                j = m - (k - 1) * (width // (2 * R))
+                assert (lo, hi) == (R * abs(j - 1), width - R * abs(j - 1))
+                new = {}
+                for o in range(lo, hi):
+                    i = o + R
+                    assert top[i] == m - 1
+                    for nb in (i - 2, i - 1, i + 1, i + 2):
+                        assert top[nb] in (m - 1, m), "neighbour level not in the struct"
+                    src = (m - 1) & 1
+                    new[i] = _h(*(s[i + d][src] for d in (-2, -1, 0, 1, 2)), m)
+                    assert (idx[i], m) not in computed
+                    computed.add((idx[i], m))
+                for i, v in new.items():
+                    s[i][m & 1] = v
+                    top[i] = m
+            for i in range(R, width + R):
+                nxt[idx[i]] = (s[i][0], s[i][1], top[i])
+        cur = nxt
+    assert all(c[2] == levels for c in cur) and len(computed) == n * levels
+    return [c[levels & 1] for c in cur]
+
+
+@pytest.mark.parametrize("n,width", [(8, 4), (16, 4), (16, 8), (24, 12), (64, 16), (96, 32)])
+def test_radius2_schedule_equals_stepping(n, width):
+    rng = random.Random(n * 77 + width)
+    u0 = [rng.getrandbits(60) for _ in range(n)]
+    h = width // 4
+    for levels in sorted({0, 1, 2, h, h + 1, 3 * h + 1, rng.randint(1, 6 * h)}):
+        assert _swept_r2(u0, levels, width) == _naive_r2(u0, levels)
+
+
+def _flat_update(t, m, c, nb):
+    """Flattened Euler sub-steps: t = 0 predictor (Q0 of 5 cells -> Q1),
+    t = 1 corrector (Q1 of 5 cells and own Q0 -> Q0)."""
+    if t == 0:
+        return "Q1", _h(*(x["Q0"] for x in nb), m)
+    return "Q0", _h(c["Q0"], *(x["Q1"] for x in nb), m)
+
+
+def _naive_flat(q0, levels):
+    n = len(q0)
+    st = [{"Q0": v, "Q1": 0} for v in q0]
+    for m in range(1, levels + 1):
+        t = (m - 1) & 1
+        upd = [_flat_update(t, m, st[i], [st[(i + d) % n] for d in (-2, -1, 0, 1, 2)])
+               for i in range(n)]
+        for i, (f, v) in enumerate(upd):
+            st[i][f] = v
+    return [c["Q0"] for c in st]
+
+
+def _swept_flat(q0, levels, width):
+    n, R = len(q0), 2
+    cur = [({"Q0": v, "Q1": 0}, 0) for v in q0]
+    for k, k_count, off, first, last in _phases(levels, width, R):
+        nxt = [None] * n
+        for t0 in range(off, off + n, width):
+            idx = [(t0 - R + i) % n for i in range(width + 2 * R)]
+            st = [dict(cur[g][0]) for g in idx]
+            top = [cur[g][1] for g in idx]
+            for m in range(first, last + 1):
+                lo, hi = sw.sw_phase_interval(k, levels, width, m, R)
+                upd = {}
+                for o in range(lo, hi):
+                    i = o + R
+                    assert top[i] == m - 1
+                    assert all(top[i + d] in (m - 1, m) for d in (-2, -1, 1, 2))
+                    upd[i] = _flat_update((m - 1) & 1, m, st[i], [st[i + d] for d in (-2, -1, 0, 1, 2)])
+                for i, (f, v) in upd.items():
+                    st[i][f] = v
+                    top[i] = m
+            for i in range(R, width + R):
+                nxt[idx[i]] = (st[i], top[i])
+        cur = nxt
+    return [c[0]["Q0"] for c in cur]
+
+
+@pytest.mark.parametrize("n,width", [(8, 4), (16, 8), (32, 8), (48, 16)])
+def test_flat_struct_schedule_equals_stepping(n, width):
+    rng = random.Random(5 * n + width)
+    q0 = [rng.getrandbits(60) for _ in range(n)]
+    for steps in sorted({0, 1, 2, 3, rng.randint(1, width)}):
+        assert _swept_flat(q0, 2 * steps, width) == _naive_flat(q0, 2 * steps)
