@@ -51,11 +51,24 @@ STRUCT_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 12, sw.EULER_F64: 56, sw.EULER_F32
 # algorithmic HBM bytes per cell-update of the classic path
 NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32: 140,
                sw.EULER_F64_FLAT: 120, sw.EULER_F32_FLAT: 84}
-# binary64 operations per heat cell-update: 3 subtractions/additions of the
-# difference form, one multiply by r, one add (no fused multiply-add)
-HEAT_FLOPS = 5
-# binary64 add/mul issue rate without FMA: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-FP64_NONFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+# arithmetic operations per cell-update (one cell, one time step), counted from
+# the scheme: every add, subtract, multiply, divide, square root, comparison and
+# absolute value is one operation.  Heat: two differences, their sum, the
+# multiply by r and the add (5); binary32 adds four Kahan operations.  Euler,
+# per half step and cell: pressure 5, ratio 3, one face flux 64 (reciprocal
+# ratio, two limiters, reconstruction, two primitive recoveries, two sound
+# speeds, the two physical fluxes, the Rusanov dissipation), update 9;
+# binary32 adds three Kahan operations per component in the corrector.
+OPS_PER_UPDATE = {sw.HEAT_F64: 5, sw.HEAT_F32: 8, sw.EULER_F64: 162, sw.EULER_F32: 171,
+                  sw.EULER_F64_FLAT: 162, sw.EULER_F32_FLAT: 171}
+# vector lane-operation issue rate with no fused or packed forms (the kernels
+# use neither): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# LDS port: 128 bytes per clock per CU
+LDS_PEAK_GBS = 256 * 128 * 2.4e9 / 1e9
+# LDS bytes per heat cell-update of the level sweep: three neighbour reads and
+# one write (binary32: plus the compensation read and write)
+LDS_BYTES_PER_UPDATE = {sw.HEAT_F64: 32, sw.HEAT_F32: 24}
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = {
     sw.HEAT_F64: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h"],
@@ -77,18 +90,18 @@ def kernel_source_hash(eq) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(work, eq, width):
-    """HBM bytes per phase launch measured with rocprofv3 counters (see
-    profiles/*_hbm_traffic.json), or None when absent or taken on other
-    kernel sources / another configuration."""
-    path = os.path.join(PROFILES, f"{work.name}_hbm_traffic.json")
+def measured_counters(work, eq, width):
+    """Per-launch hardware counters of the swept phase kernel taken with
+    rocprofv3 on this workload (profiles/<workload>_counters.txt), or None when
+    absent or taken on other kernel sources or another width."""
+    path = os.path.join(PROFILES, f"{work.name}_counters.txt")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_sha256") != kernel_source_hash(eq) or rec.get("width") != width:
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
 def log(*a):
@@ -132,15 +145,27 @@ def cpu_baseline(work, eq, budget_s):
     chunk = 20
     done, t_used = 0, 0.0
     if eq in (sw.HEAT_F64, sw.HEAT_F32):
-        run = oracle.heat_f64
         arg = work.dt / (work.dx * work.dx)
         cells = work.n
+        if eq == sw.HEAT_F64:
+            run = oracle.heat_f64
+        else:
+            q = (q.astype(np.float32), np.zeros(q.shape, np.float32))
+
+            def run(s, k, a):
+                return oracle.heat_f32(s[0], s[1], k, a)
     else:
         # one Sod tile: the tiled problem is periodic with the tile's period
         q = q[:, : work.tile]
-        run = oracle.euler_f64
         arg = work.dt / work.dx
         cells = work.tile
+        if sw.is_f64(eq):
+            run = oracle.euler_f64
+        else:
+            q = (q.astype(np.float32), np.zeros(q.shape, np.float32))
+
+            def run(s, k, a):
+                return oracle.euler_f32(s[0], s[1], k, a)
     while t_used < budget_s and done < work.steps:
         t0 = time.perf_counter()
         q = run(q, chunk, arg)
@@ -151,7 +176,8 @@ def cpu_baseline(work, eq, budget_s):
         "unit": "cell-updates/s",
         "cores": oracle.threads_used(),
         "kind": "oracle",
-        "sample": f"{cells} cells x {done} time steps of the same workload, binary64, "
+        "sample": f"{cells} cells x {done} time steps of the same workload, "
+                  f"{'binary64' if sw.is_f64(eq) else 'binary32 + Kahan'}, "
                   f"{t_used:.1f} s wall on {oracle.threads_used()} OpenMP threads",
     }
 
@@ -216,19 +242,28 @@ def main() -> int:
     achieved_gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
     hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes}
-    traffic = measured_traffic(work, eq, width)
-    if eq in (sw.HEAT_F64, sw.HEAT_F32):
-        # ALU-bound by design: the binary64 add/mul rate is the ceiling
-        achieved = value * HEAT_FLOPS / 1e12
-        roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_NONFMA_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / FP64_NONFMA_PEAK_TFLOPS,
-                    "traffic": traffic,
-                    "flops_per_launch": updates * HEAT_FLOPS / phases}
-    else:
-        roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic}
-    roofline.update({"kernel": "swept phase kernel", "launch_ms": launch_ms,
-                     "launches_per_step": phases, "hbm": hbm})
+    counters = measured_counters(work, eq, width)
+    traffic = counters.get("hbm_bytes_per_launch") if counters else None
+    ops = OPS_PER_UPDATE[eq]
+    achieved = value * ops / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
+                "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                "ops_per_cell_update": ops, "flops_per_launch": updates * ops / phases,
+                "kernel": "swept phase kernel", "launch_ms": launch_ms,
+                "launches_per_step": phases, "hbm": hbm}
+    if eq in LDS_BYTES_PER_UPDATE:
+        lds_gbs = value * LDS_BYTES_PER_UPDATE[eq] / 1e9
+        roofline["lds"] = {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                           "frac": lds_gbs / LDS_PEAK_GBS,
+                           "bytes_per_cell_update": LDS_BYTES_PER_UPDATE[eq]}
+    if counters and counters.get("valu_insts_per_launch"):
+        # wave-level VALU instructions issued per second over the chip's issue
+        # rate (one wave instruction per clock per CU)
+        rate = counters["valu_insts_per_launch"] / (launch_ms * 1e-3)
+        roofline["valu_issue"] = {
+            "insts_per_cell_update": counters["valu_insts_per_launch"] * 64 / (updates / phases),
+            "achieved": rate / 1e9, "peak": 256 * 2.4, "unit": "G wave-insts/s",
+            "frac": rate / (256 * 2.4e9)}
     out = {
         "metric": METRIC,
         "value": value,

@@ -74,7 +74,14 @@ int struct_bytes(int eq)
     }
 }
 
-int preferred_width(int eq) { return is_euler(eq) ? 256 : 1024; }
+// measured on MI355X (2^22 cells): heat best at 1024, lengthened Euler at
+// 512 with 256-thread workgroups; sw_autotune refines per grid size
+int preferred_width(int eq)
+{
+    if (!is_euler(eq))
+        return 1024;
+    return is_flat(eq) ? 256 : 512;
+}
 
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

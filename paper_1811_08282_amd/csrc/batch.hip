@@ -123,6 +123,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_persistent(BatchTables 
             jb.j_last = pr.j_last;
             jb.first = (k == 1);
             jb.last = (k == P.phases) && !P.single_phase;
+            jb.final_level = P.final_level;
             switch (P.eq) {
             case 0: heat_f64_tile<kBatchThreads>(jb, lds); break;
             case 1: heat_f32_tile<kBatchThreads>(jb, (float *)lds); break;

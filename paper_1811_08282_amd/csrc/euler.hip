@@ -10,7 +10,7 @@ namespace {
 
 constexpr int kNaiveBlock = 256;
 
-template <int NT>
+template <int NT, int WT>
 __global__ void __launch_bounds__(NT)
 k_euler_f64_phase(double *__restrict__ state, const double *__restrict__ ws_in,
                   double *__restrict__ ws_out, int64_t n, int w, int64_t offset, int64_t base,
@@ -18,11 +18,11 @@ k_euler_f64_phase(double *__restrict__ state, const double *__restrict__ ws_in,
 {
     extern __shared__ double lds[];
     TileJob jb{state, ws_in, ws_out, n, offset + (int64_t)blockIdx.x * w - 1, base, lam, w,
-               j_first, j_last, first, last};
-    euler_f64_tile<NT>(jb, lds);
+               j_first, j_last, first, last, base + j_last};
+    euler_f64_tile<NT, WT>(jb, lds);
 }
 
-template <int NT>
+template <int NT, int WT>
 __global__ void __launch_bounds__(NT)
 k_euler_f32_phase(float *__restrict__ state, const void *__restrict__ ws_in,
                   void *__restrict__ ws_out, int64_t n, int w, int64_t offset, int64_t base,
@@ -30,8 +30,8 @@ k_euler_f32_phase(float *__restrict__ state, const void *__restrict__ ws_in,
 {
     extern __shared__ double ldsd[];
     TileJob jb{state, ws_in, ws_out, n, offset + (int64_t)blockIdx.x * w - 1, base, (double)lam,
-               w, j_first, j_last, first, last};
-    euler_f32_tile<NT>(jb, ldsd);
+               w, j_first, j_last, first, last, base + j_last};
+    euler_f32_tile<NT, WT>(jb, ldsd);
 }
 
 // Classic pressure-ratio sub-step: q (3n) -> pr (n).  Block-local pressures.
@@ -150,10 +150,27 @@ hipError_t euler_f64_swept_phase(const PhaseLaunch &p, double *state, const doub
                                  double *ws_out, double lam, hipStream_t s)
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellEulerF64;
-    return launch_by_threads(p.threads, k_euler_f64_phase<64>, k_euler_f64_phase<128>,
-                             k_euler_f64_phase<256>, dim3((unsigned)(p.n / p.w)), lds, s, state,
-                             ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
-                             (int)p.first, (int)p.last);
+    const dim3 g = dim3((unsigned)(p.n / p.w));
+    if (p.threads == 256) {
+        switch (p.w) {  // widths with compile-time LDS offsets
+        case 128: return launch_kernel(k_euler_f64_phase<256, 128>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        case 256: return launch_kernel(k_euler_f64_phase<256, 256>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        case 512: return launch_kernel(k_euler_f64_phase<256, 512>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        case 1024: return launch_kernel(k_euler_f64_phase<256, 1024>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        default: break;
+        }
+    }
+    return launch_by_threads(p.threads, k_euler_f64_phase<64, 0>, k_euler_f64_phase<128, 0>, k_euler_f64_phase<256, 0>, g, lds, s,
+        state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam, (int)p.first,
+        (int)p.last);
 }
 
 hipError_t euler_f64_naive_substep(int t, double *q0, double *q1, double *pr, int64_t n,
@@ -173,10 +190,24 @@ hipError_t euler_f32_swept_phase(const PhaseLaunch &p, float *state, const void 
                                  void *ws_out, float lam, hipStream_t s)
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellEulerF32;
-    return launch_by_threads(p.threads, k_euler_f32_phase<64>, k_euler_f32_phase<128>,
-                             k_euler_f32_phase<256>, dim3((unsigned)(p.n / p.w)), lds, s, state,
-                             ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
-                             (int)p.first, (int)p.last);
+    const dim3 g = dim3((unsigned)(p.n / p.w));
+    if (p.threads == 256) {
+        switch (p.w) {  // widths with compile-time LDS offsets
+        case 256: return launch_kernel(k_euler_f32_phase<256, 256>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        case 512: return launch_kernel(k_euler_f32_phase<256, 512>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        case 1024: return launch_kernel(k_euler_f32_phase<256, 1024>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        default: break;
+        }
+    }
+    return launch_by_threads(p.threads, k_euler_f32_phase<64, 0>, k_euler_f32_phase<128, 0>, k_euler_f32_phase<256, 0>, g, lds, s,
+        state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam, (int)p.first,
+        (int)p.last);
 }
 
 hipError_t euler_f32_naive_substep(int t, float *q0c, float *q1, double *pr, int64_t n, float lam,

@@ -20,7 +20,9 @@
 // one struct per cell carries both of its latest levels.
 //
 // Face sharing: inside a level every face flux is computed once into LDS and
-// used by both cells it separates; pressures likewise for the ratio.
+// used by both cells it separates.  Each cell's pressure is kept in LDS and
+// refreshed whenever its state changes, so a ratio sub-step reads three
+// stored pressures instead of recomputing them.
 #pragma once
 
 #include <math.h>
@@ -76,18 +78,36 @@ __device__ __forceinline__ void face64(double a0, double a1, double a2, double b
     f2 = 0.5 * ((l2 + pl) * vl + (r2 + pr) * vr) - hs * (r2 - l2);
 }
 
-// LDS: q0[3][wp] q1[3][wp] pr[wp] tmp[3][wp]   (doubles, wp = w + 2)
-// ws layout: Q0[3][n], Q1[3][n], Pr[n] (doubles)
-template <int NT>
+// top level of LDS cell i when a phase starts (halos: the previous peak)
+__device__ __forceinline__ int64_t entry_level(const TileJob &jb, int i, int w)
+{
+    if (jb.first)
+        return 0;
+    const int64_t cap = jb.final_level;
+    if (i == 0 || i == w + 1)
+        return jb.base < cap ? jb.base : cap;
+    const int o = i - 1;
+    const int p = (o + 1 < w - o) ? o + 1 : w - o;
+    int64_t lv = jb.base + 1 - p;
+    lv = lv < 0 ? 0 : lv;
+    return lv < cap ? lv : cap;
+}
+
+// LDS: q0[3][wp] q1[3][wp] pr[wp] P[wp] tmp[3][wp]   (doubles, wp = w + 2)
+// P holds the pressure of the state the next ratio sub-step reads: p(Q0) for
+// a cell whose level is 0 or 1 mod 4, p(Q1) for 2 or 3 mod 4.  It is set
+// from the entry level at load and refreshed by every predictor/corrector.
+template <int NT, int WT = 0>
 __device__ __forceinline__ void euler_f64_tile(const TileJob &jb, double *lds)
 {
-    const int w = jb.w;
+    const int w = WT > 0 ? WT : jb.w;  // compile-time width when WT > 0
     const int wp = w + 2;
     const int64_t n = jb.n;
     double *q0 = lds;
     double *q1 = lds + 3 * wp;
     double *pr = lds + 6 * wp;
-    double *tmp = lds + 7 * wp;
+    double *pp = lds + 7 * wp;
+    double *tmp = lds + 8 * wp;
     double *state = (double *)jb.state;
     const double *ws_in = (const double *)jb.ws_in;
     double *ws_out = (double *)jb.ws_out;
@@ -98,9 +118,12 @@ __device__ __forceinline__ void euler_f64_tile(const TileJob &jb, double *lds)
         if (jb.first) {
             for (int k = 0; k < 3; ++k)
                 q0[k * wp + i] = state[k * n + g];
+            pp[i] = pressure64(q0[i], q0[wp + i], q0[2 * wp + i]);
         } else {
             for (int k = 0; k < 7; ++k)
                 lds[k * wp + i] = ws_in[k * n + g];
+            const double *q = ((entry_level(jb, i, w) & 2) == 0) ? q0 : q1;
+            pp[i] = pressure64(q[i], q[wp + i], q[2 * wp + i]);
         }
     }
     __syncthreads();
@@ -111,30 +134,26 @@ __device__ __forceinline__ void euler_f64_tile(const TileJob &jb, double *lds)
         const int a = window_margin(j);
         const int lo = a + 1, hi = w - a + 1;  // active LDS indices [lo, hi)
         const int t = (int)((jb.base + j - 1) & 3);
-        const double *q = (t < 2) ? q0 : q1;
         if ((t & 1) == 0) {
-            for (int i = lo - 1 + tid; i < hi + 1; i += NT)
-                tmp[i] = pressure64(q[i], q[wp + i], q[2 * wp + i]);
-            __syncthreads();
             for (int i = lo + tid; i < hi; i += NT)
-                pr[i] = ratio(tmp[i - 1], tmp[i], tmp[i + 1]);
+                pr[i] = ratio(pp[i - 1], pp[i], pp[i + 1]);
             __syncthreads();
         } else {
+            const double *q = (t == 1) ? q0 : q1;
             // tmp[k][i]: flux through the face between LDS cells i-1 and i
             for (int i = lo + tid; i < hi + 1; i += NT)
                 face64(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
                        pr[i - 1], pr[i], tmp[i], tmp[wp + i], tmp[2 * wp + i]);
             __syncthreads();
-            if (t == 1) {
-                for (int i = lo + tid; i < hi; i += NT)
-                    for (int k = 0; k < 3; ++k)
-                        q1[k * wp + i] =
-                            q0[k * wp + i] + half_lam * (tmp[k * wp + i] - tmp[k * wp + i + 1]);
-            } else {
-                for (int i = lo + tid; i < hi; i += NT)
-                    for (int k = 0; k < 3; ++k)
-                        q0[k * wp + i] =
-                            q0[k * wp + i] + lam * (tmp[k * wp + i] - tmp[k * wp + i + 1]);
+            double *dst = (t == 1) ? q1 : q0;
+            const double c = (t == 1) ? half_lam : lam;
+            for (int i = lo + tid; i < hi; i += NT) {
+                double nq[3];
+                for (int k = 0; k < 3; ++k)
+                    nq[k] = q0[k * wp + i] + c * (tmp[k * wp + i] - tmp[k * wp + i + 1]);
+                for (int k = 0; k < 3; ++k)
+                    dst[k * wp + i] = nq[k];
+                pp[i] = pressure64(nq[0], nq[1], nq[2]);
             }
             __syncthreads();
         }
@@ -194,19 +213,18 @@ __device__ __forceinline__ float kahan_add(float q, float d, float &c)
     return t;
 }
 
-// LDS: pr[wp] (double), tmp[3][wp] (float; reused as wp doubles for the
-// pressures), q0[3][wp], c[3][wp], q1[3][wp] (float).
+// LDS: pr[wp], P[wp] (double), tmp[3][wp], q0[3][wp], c[3][wp], q1[3][wp] (float).
 // ws layout: q0[3][n], c[3][n], q1[3][n] floats, then pr[n] doubles at byte 36n.
-template <int NT>
+template <int NT, int WT = 0>
 __device__ __forceinline__ void euler_f32_tile(const TileJob &jb, double *ldsd)
 {
-    const int w = jb.w;
+    const int w = WT > 0 ? WT : jb.w;  // compile-time width when WT > 0
     const int wp = w + 2;
     const int64_t n = jb.n;
     double *pr = ldsd;
-    double *ptmp = ldsd + wp;
-    float *ftmp = (float *)(ldsd + wp);
-    float *fst = (float *)(ldsd + wp) + 3 * wp;  // q0[3], c[3], q1[3]
+    double *pp = ldsd + wp;
+    float *ftmp = (float *)(ldsd + 2 * wp);
+    float *fst = ftmp + 3 * wp;  // q0[3], c[3], q1[3]
     float *q0 = fst;
     float *cc = fst + 3 * wp;
     float *q1 = fst + 6 * wp;
@@ -222,10 +240,13 @@ __device__ __forceinline__ void euler_f32_tile(const TileJob &jb, double *ldsd)
         if (jb.first) {
             for (int k = 0; k < 6; ++k)
                 fst[k * wp + i] = state[k * n + g];
+            pp[i] = pressure32(q0[i], q0[wp + i], q0[2 * wp + i]);
         } else {
             for (int k = 0; k < 9; ++k)
                 fst[k * wp + i] = win[k * n + g];
             pr[i] = win_pr[g];
+            const float *q = ((entry_level(jb, i, w) & 2) == 0) ? q0 : q1;
+            pp[i] = pressure32(q[i], q[wp + i], q[2 * wp + i]);
         }
     }
     __syncthreads();
@@ -236,32 +257,39 @@ __device__ __forceinline__ void euler_f32_tile(const TileJob &jb, double *ldsd)
         const int a = window_margin(j);
         const int lo = a + 1, hi = w - a + 1;
         const int t = (int)((jb.base + j - 1) & 3);
-        const float *q = (t < 2) ? q0 : q1;
         if ((t & 1) == 0) {
-            for (int i = lo - 1 + tid; i < hi + 1; i += NT)
-                ptmp[i] = pressure32(q[i], q[wp + i], q[2 * wp + i]);
-            __syncthreads();
             for (int i = lo + tid; i < hi; i += NT)
-                pr[i] = ratio(ptmp[i - 1], ptmp[i], ptmp[i + 1]);
+                pr[i] = ratio(pp[i - 1], pp[i], pp[i + 1]);
             __syncthreads();
         } else {
+            const float *q = (t == 1) ? q0 : q1;
             for (int i = lo + tid; i < hi + 1; i += NT)
                 face32(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
                        pr[i - 1], pr[i], ftmp[i], ftmp[wp + i], ftmp[2 * wp + i]);
             __syncthreads();
             if (t == 1) {
-                for (int i = lo + tid; i < hi; i += NT)
+                for (int i = lo + tid; i < hi; i += NT) {
+                    float nq[3];
                     for (int k = 0; k < 3; ++k)
-                        q1[k * wp + i] =
-                            q0[k * wp + i] + half_lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]);
+                        nq[k] = q0[k * wp + i] +
+                                half_lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]);
+                    for (int k = 0; k < 3; ++k)
+                        q1[k * wp + i] = nq[k];
+                    pp[i] = pressure32(nq[0], nq[1], nq[2]);
+                }
             } else {
-                for (int i = lo + tid; i < hi; i += NT)
+                for (int i = lo + tid; i < hi; i += NT) {
+                    float nq[3];
                     for (int k = 0; k < 3; ++k) {
                         float c = cc[k * wp + i];
-                        q0[k * wp + i] = kahan_add(
-                            q0[k * wp + i], lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]), c);
+                        nq[k] = kahan_add(q0[k * wp + i],
+                                          lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]), c);
                         cc[k * wp + i] = c;
                     }
+                    for (int k = 0; k < 3; ++k)
+                        q0[k * wp + i] = nq[k];
+                    pp[i] = pressure32(nq[0], nq[1], nq[2]);
+                }
             }
             __syncthreads();
         }

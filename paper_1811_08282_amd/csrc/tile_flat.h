@@ -26,10 +26,10 @@ constexpr int kFlatRadius = 2;
 
 // LDS: q0[3][wp] q1[3][wp] P[wp] R[wp] tmp[3][wp]   (doubles, wp = w + 4)
 // ws layout: Q0[3][n], Q1[3][n]
-template <int NT>
+template <int NT, int WT = 0>
 __device__ __forceinline__ void flat_f64_tile(const TileJob &jb, double *lds)
 {
-    const int w = jb.w;
+    const int w = WT > 0 ? WT : jb.w;  // compile-time width when WT > 0
     const int wp = w + 2 * kFlatRadius;
     const int64_t n = jb.n;
     double *q0 = lds;
@@ -98,10 +98,10 @@ __device__ __forceinline__ void flat_f64_tile(const TileJob &jb, double *lds)
 
 // LDS: P[wp], R[wp] (double), tmp[3][wp], q0[3][wp], c[3][wp], q1[3][wp] (float)
 // ws layout: q0[3][n], c[3][n], q1[3][n] floats
-template <int NT>
+template <int NT, int WT = 0>
 __device__ __forceinline__ void flat_f32_tile(const TileJob &jb, double *ldsd)
 {
-    const int w = jb.w;
+    const int w = WT > 0 ? WT : jb.w;  // compile-time width when WT > 0
     const int wp = w + 2 * kFlatRadius;
     const int64_t n = jb.n;
     double *pp = ldsd;

@@ -49,14 +49,14 @@ def test_state_and_workspace_sizes():
 
 
 def test_width_limits():
-    for eq, per_cell, rad in ((sw.HEAT_F64, 16, 1), (sw.HEAT_F32, 12, 1), (sw.EULER_F64, 80, 1),
-                              (sw.EULER_F32, 56, 1), (sw.EULER_F64_FLAT, 88, 2),
+    for eq, per_cell, rad in ((sw.HEAT_F64, 16, 1), (sw.HEAT_F32, 12, 1), (sw.EULER_F64, 88, 1),
+                              (sw.EULER_F32, 64, 1), (sw.EULER_F64_FLAT, 88, 2),
                               (sw.EULER_F32_FLAT, 64, 2)):
         wmax = sw.sw_max_width(eq)
         assert wmax % (2 * rad) == 0 and (wmax + 2 * rad) * per_cell <= 160 * 1024
         assert wmax <= 8192
     assert sw.sw_default_width(sw.HEAT_F64, 1 << 22) == 1024
-    assert sw.sw_default_width(sw.EULER_F64, 1 << 22) == 256
+    assert sw.sw_default_width(sw.EULER_F64, 1 << 22) == 512
     assert sw.sw_default_width(sw.HEAT_F64, 1000) == 500  # largest even divisor with n/W >= 2
     assert sw.sw_default_width(sw.HEAT_F64, 1001) == 0    # odd: no even divisor
     assert sw.sw_default_width(sw.HEAT_F64, 6) == 2
