@@ -92,9 +92,9 @@ def kernel_source_hash(eq) -> str:
 
 def measured_counters(work, eq, width):
     """Per-launch hardware counters of the swept phase kernel taken with
-    rocprofv3 on this workload (profiles/<workload>_counters.txt), or None when
+    rocprofv3 on this workload (profiles/<workload>_phase_counters.txt), or None when
     absent or taken on other kernel sources or another width."""
-    path = os.path.join(PROFILES, f"{work.name}_counters.txt")
+    path = os.path.join(PROFILES, f"{work.name}_phase_counters.txt")
     if not os.path.exists(path):
         return None
     with open(path) as f:
