@@ -161,7 +161,6 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
     b.run(stream)
     assert b.wait(stream) == sw.SW_OK, sw.last_error()
     widths = [b.width(i) for i in range(len(specs))]
-    b.close()
     order = np.argsort([p.n for p in probs], kind="stable")
     check_oracle = set(order[:16].tolist())
     for i, (p, s) in enumerate(zip(probs, specs)):
@@ -179,3 +178,15 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
             else:
                 q, c = oracle.euler_f32(hosts[i][:3], hosts[i][3:], 5000, 0.1)
                 assert np.array_equal(got[:3], q) and np.array_equal(got[3:], c)
+    # throughput of one more replay of the captured launch (5000 further steps)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    b.run(stream)
+    stop.record()
+    assert b.wait(stream) == sw.SW_OK, sw.last_error()
+    ms = start.elapsed_time(stop)
+    cells = sum(p.n for p in probs)
+    record(f"batch_4096x5000_{'f64' if sw.is_f64(eq_heat) else 'f32'}", ms=ms, cells=cells,
+           cell_updates_per_s=cells * 5000 / (ms * 1e-3))
+    b.close()
