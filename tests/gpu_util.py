@@ -47,12 +47,11 @@ def rel_inf(a, b):
 
 
 def record(name, **values):
-    """Append a measured figure (e.g. an error against the oracle) to
-    gpurun_out/measured.jsonl when that folder exists, and print it."""
+    """Print a measured figure (e.g. an error against the oracle) and append
+    it as one JSON line to the file named by SWEPT_RECORD_FILE, if set."""
     line = json.dumps(dict(name=name, **values))
     print("[measured]", line, flush=True)
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    out = os.path.join(root, "gpurun_out")
-    if os.path.isdir(out):
-        with open(os.path.join(out, "measured.jsonl"), "a") as f:
+    path = os.environ.get("SWEPT_RECORD_FILE")
+    if path:
+        with open(path, "a") as f:
             f.write(line + "\n")
