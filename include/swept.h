@@ -190,8 +190,11 @@ int sw_phase_interval(int64_t k, int64_t final_level, int width, int radius, int
 int sw_autotune(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream, sw_opts *best,
                 double *best_ms_per_update);
 
-/* The recorded width (and workgroup size) of (current device, eq, n_cells);
- * SW_ERR_UNSUPPORTED when none is recorded. */
+/* The width (and workgroup size) recorded for exactly (current device, eq,
+ * n_cells); SW_ERR_UNSUPPORTED when none is.  A cell count without a record
+ * of its own takes, in swept_solve and sw_batch_create, the latest record of
+ * its size class floor(log2 n_cells) for the same device and eq when that
+ * width is valid for it. */
 int sw_tuned_width(int eq, int64_t n_cells, int *width, int *threads);
 
 /* Forget every recorded width of this process (the cache file is kept). */
@@ -249,6 +252,27 @@ void sw_batch_destroy(sw_batch batch);
 
 /* create + run + wait + destroy. */
 int swept_solve_batch(int n_problems, const sw_problem *problems, sw_stream stream);
+
+/* Autotuner of the batched launch (the paper's advice to tune the block
+ * width on a few steps before a long run, Sec. 6, applied to a batch).  The
+ * batch is timed on scratch copies of the problem states (allocated, copied
+ * and freed here; the caller's states are only read), every probe running
+ * the same steps per problem: min(n_steps, probe_steps), or with
+ * probe_steps = 0 enough steps for four phases at the widest power-of-two
+ * width of the problem's equation.
+ *  1. widths, one equation at a time: every problem of that equation given
+ *     with width 0 takes the largest valid width not above a cap, for caps
+ *     64, 128, ... up to the widest tile; the fastest cap is kept;
+ *  2. resident workgroups per CU: 1, 2, ... up to the occupancy limit.
+ * On success the chosen widths are written into problems[i].width for every
+ * problem given with width 0, best->blocks_per_cu is set (0 = occupancy
+ * limit was fastest; wait_limit_us = 0) and *best_ms_per_update (may be
+ * NULL) gets the fastest probe's time per cell-update.  Synchronous; not
+ * allowed during stream capture (SW_ERR_CAPTURE); needs device memory for
+ * one copy of every state plus one batch's working arrays (SW_ERR_NOMEM
+ * otherwise).  Other errors as sw_batch_create. */
+int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
+                      sw_stream stream, sw_batch_opts *best, double *best_ms_per_update);
 
 /* Previous-phase tiles that work item (phase, tile) of a batched problem
  * with `tiles` tiles waits for (host mirror of the device rule, no HIP call):

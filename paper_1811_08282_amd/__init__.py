@@ -116,6 +116,9 @@ def load() -> ctypes.CDLL:
     lib.swept_solve_batch.restype = i32
     lib.sw_batch_item_deps.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i32)]
     lib.sw_batch_item_deps.restype = i32
+    lib.sw_batch_autotune.argtypes = [i32, ctypes.POINTER(sw_problem), i64, vp,
+                                      ctypes.POINTER(sw_batch_opts), ctypes.POINTER(d)]
+    lib.sw_batch_autotune.restype = i32
     _lib = lib
     return lib
 
@@ -278,6 +281,24 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def sw_batch_autotune(problems, probe_steps=0, stream=None):
+    """Tune the batched launch (see include/swept.h): the problems' states are
+    only read; every problem given with width 0 gets the chosen width written
+    back into its dict.  Returns (blocks_per_cu, ms per cell-update of the
+    fastest probe); raises on failure."""
+    arr = problem_array(problems)
+    best = sw_batch_opts()
+    ms = ctypes.c_double()
+    rc = load().sw_batch_autotune(len(arr), arr, int(probe_steps), stream, ctypes.byref(best),
+                                  ctypes.byref(ms))
+    if rc:
+        raise SweptError(rc, last_error())
+    for p, a in zip(problems, arr):
+        if isinstance(p, dict) and not p.get("width"):
+            p["width"] = a.width
+    return best.blocks_per_cu, ms.value
 
 
 def swept_solve_batch(problems, stream=None) -> int:

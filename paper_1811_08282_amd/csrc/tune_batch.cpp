@@ -51,7 +51,26 @@ struct TuneEntry {
 
 std::mutex g_tune_mutex;
 std::map<std::tuple<std::string, int, int64_t>, TuneEntry> g_tune;
+// the latest entry recorded per (arch, eq, size class floor(log2 n)): used for
+// cell counts of that class that have no entry of their own
+std::map<std::tuple<std::string, int, int>, TuneEntry> g_tune_class;
 bool g_tune_loaded = false;
+
+int size_class(int64_t n)
+{
+    int c = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++c;
+    }
+    return c;
+}
+
+void record_tune_locked(const std::string &arch, int eq, int64_t n, const TuneEntry &e)
+{
+    g_tune[std::make_tuple(arch, eq, n)] = e;
+    g_tune_class[std::make_tuple(arch, eq, size_class(n))] = e;
+}
 
 std::string arch_name(int dev)
 {
@@ -88,7 +107,7 @@ void load_tune_file_locked()
     double ms;
     while (fscanf(f, "%63s %d %lld %d %d %lf", arch, &eq, &n, &w, &t, &ms) == 6) {
         if (valid_eq(eq) && width_ok(eq, n, w) && (t == 64 || t == 128 || t == 256))
-            g_tune[std::make_tuple(std::string(arch), eq, (int64_t)n)] = TuneEntry{w, t, ms};
+            record_tune_locked(std::string(arch), eq, (int64_t)n, TuneEntry{w, t, ms});
     }
     fclose(f);
 }
@@ -116,11 +135,18 @@ int chosen_width(int dev, int eq, int64_t n, int *threads)
                 (void)hipGetLastError();
                 dev = 0;
             }
-            auto it = g_tune.find(std::make_tuple(arch_name(dev), eq, n));
+            const std::string arch = arch_name(dev);
+            auto it = g_tune.find(std::make_tuple(arch, eq, n));
             if (it != g_tune.end()) {
                 if (threads)
                     *threads = it->second.threads;
                 return it->second.width;
+            }
+            auto ic = g_tune_class.find(std::make_tuple(arch, eq, size_class(n)));
+            if (ic != g_tune_class.end() && width_ok(eq, n, ic->second.width)) {
+                if (threads)
+                    *threads = ic->second.threads;
+                return ic->second.width;
             }
         }
     }
@@ -311,7 +337,7 @@ int sw_autotune(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream, 
         std::lock_guard<std::mutex> lock(g_tune_mutex);
         load_tune_file_locked();
         const std::string arch = arch_name(dev);
-        g_tune[std::make_tuple(arch, eq, n_cells)] = top;
+        record_tune_locked(arch, eq, n_cells, top);
         store_tune_file_locked(arch, eq, n_cells, top);
     }
     best->width = top.width;
@@ -347,6 +373,7 @@ void sw_tune_clear(void)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tune.clear();
+    g_tune_class.clear();
     g_tune_loaded = true;  // do not reload the file after an explicit clear
 }
 
@@ -581,6 +608,197 @@ int swept_solve_batch(int n_problems, const sw_problem *problems, sw_stream stre
     const std::string msg = last_error();
     sw_batch_destroy(b);
     return rc ? fail(rc, "%s", msg.c_str()) : ok();
+}
+
+int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
+                      sw_stream stream, sw_batch_opts *best, double *best_ms_per_update)
+{
+    if (!best)
+        return fail(SW_ERR_ARG, "best is NULL");
+    if (n_problems < 1 || !problems)
+        return fail(SW_ERR_ARG, "empty problem list");
+    if (probe_steps < 0 || probe_steps > 1000000)
+        return fail(SW_ERR_ARG, "probe_steps out of range");
+    for (int i = 0; i < n_problems; ++i) {
+        const sw_problem &p = problems[i];
+        int rc = check_common(p.eq, p.n_cells, p.n_steps, p.dt, p.dx, p.d_state, 4);
+        if (rc)
+            return fail(rc, "problem %d: %s", i, last_error());
+        if (p.width && !width_ok(p.eq, p.n_cells, p.width))
+            return fail(SW_ERR_ARG, "problem %d: width %d invalid for n_cells %lld", i, p.width,
+                        (long long)p.n_cells);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_CAPTURE, "sw_batch_autotune cannot run during stream capture");
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_HIP, "device query failed");
+    }
+    std::vector<int> widths(n_problems);
+    for (int i = 0; i < n_problems; ++i) {
+        widths[i] = problems[i].width ? problems[i].width
+                                      : chosen_width(dev, problems[i].eq, problems[i].n_cells, nullptr);
+        if (!widths[i])
+            return fail(SW_ERR_UNSUPPORTED, "problem %d: no valid width for n_cells %lld", i,
+                        (long long)problems[i].n_cells);
+    }
+
+    // scratch copies of the states: every probe runs on these
+    std::vector<size_t> offs(n_problems);
+    size_t total = 0;
+    for (int i = 0; i < n_problems; ++i) {
+        offs[i] = total;
+        total += round_up(sw_state_bytes(problems[i].eq, problems[i].n_cells), 256);
+    }
+    char *buf = nullptr;
+    if (hipMalloc(&buf, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_NOMEM, "batch autotune scratch states (%zu bytes) failed", total);
+    }
+    int rc = SW_OK;
+    for (int i = 0; i < n_problems && rc == SW_OK; ++i) {
+        if (hipMemcpyAsync(buf + offs[i], problems[i].d_state,
+                           sw_state_bytes(problems[i].eq, problems[i].n_cells),
+                           hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(SW_ERR_HIP, "copying problem %d to the scratch state failed", i);
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == SW_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+        (void)hipGetLastError();
+        rc = fail(SW_ERR_HIP, "hipEventCreate failed");
+    }
+
+    // the same steps per problem in every probe, so that the probes do the
+    // same work: probe_steps, or (0) four phases at the widest power-of-two
+    // cap of the problem's equation
+    std::vector<int64_t> steps(n_problems);
+    double work = 0.0;
+    for (int i = 0; i < n_problems; ++i) {
+        const int e = problems[i].eq;
+        int cap = 64;
+        while (cap * 2 <= max_width(e))
+            cap *= 2;
+        const int64_t sub = substeps(e);
+        const int64_t four = (4 * (cap / (2 * radius(e))) + sub - 1) / sub;
+        steps[i] = std::min(problems[i].n_steps, probe_steps ? probe_steps : four);
+        work += (double)problems[i].n_cells * (double)steps[i];
+    }
+
+    // one probe: the batch with widths `ws` and `bpc` workgroups per CU; the
+    // result is the ms of the timed run (after one warm-up run)
+    int max_bpc = 0;
+    auto probe = [&](const std::vector<int> &ws, int bpc, double *ms_out) -> int {
+        std::vector<sw_problem> sp(problems, problems + n_problems);
+        for (int i = 0; i < n_problems; ++i) {
+            sp[i].d_state = buf + offs[i];
+            sp[i].width = ws[i];
+            sp[i].n_steps = steps[i];
+        }
+        sw_batch_opts o{bpc, 0, 0};
+        sw_batch b = nullptr;
+        int r = sw_batch_create(n_problems, sp.data(), &o, &b);
+        if (r)
+            return r;
+        int64_t items = 0;
+        int blocks = 0;
+        size_t bytes = 0;
+        sw_batch_info(b, &items, &blocks, &bytes);
+        if (bpc == 0)
+            max_bpc = std::max(1, (blocks + cus - 1) / std::max(cus, 1));
+        float ms = 0.f;
+        r = sw_batch_run(b, stream);  // warm-up
+        if (r == SW_OK)
+            r = sw_batch_wait(b, stream);
+        if (r == SW_OK && hipEventRecord(e0, s) != hipSuccess)
+            r = fail(SW_ERR_HIP, "hipEventRecord failed");
+        if (r == SW_OK)
+            r = sw_batch_run(b, stream);
+        if (r == SW_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            r = fail(SW_ERR_HIP, "batch autotune timing failed");
+        if (r == SW_OK)
+            r = sw_batch_wait(b, stream);
+        const std::string msg = last_error();
+        sw_batch_destroy(b);
+        (void)hipGetLastError();
+        if (r)
+            return fail(r, "%s", msg.c_str());
+        *ms_out = ms;
+        return SW_OK;
+    };
+
+    // 1. widths, one equation at a time: every problem of that equation that
+    //    leaves its width to the library takes the largest valid width up to
+    //    a cap; caps 64, 128, ... up to the equation's widest tile
+    double top = INFINITY;
+    if (rc == SW_OK)
+        rc = probe(widths, 0, &top);
+    std::vector<int> eqs;
+    for (int i = 0; i < n_problems; ++i)
+        if (!problems[i].width && std::find(eqs.begin(), eqs.end(), problems[i].eq) == eqs.end())
+            eqs.push_back(problems[i].eq);
+    for (size_t k = 0; k < eqs.size() && rc == SW_OK; ++k) {
+        const int e = eqs[k];
+        const int step = 2 * radius(e);
+        for (int cap = 64; cap <= max_width(e) && rc == SW_OK; cap *= 2) {
+            std::vector<int> cand = widths;
+            for (int i = 0; i < n_problems; ++i) {
+                if (problems[i].width || problems[i].eq != e)
+                    continue;
+                for (int w = cap - cap % step; w >= step; w -= step)
+                    if (width_ok(e, problems[i].n_cells, w)) {
+                        cand[i] = w;
+                        break;
+                    }
+            }
+            if (cand == widths)
+                continue;
+            double t = 0.0;
+            rc = probe(cand, 0, &t);
+            if (rc == SW_OK && t < top) {
+                top = t;
+                widths = cand;
+            }
+        }
+    }
+    // 2. resident workgroups per CU for those widths (0 = occupancy limit)
+    int top_bpc = 0;
+    if (rc == SW_OK)
+        rc = probe(widths, 0, &top);  // also sets max_bpc for these widths
+    for (int bpc = 1; bpc < max_bpc && rc == SW_OK; ++bpc) {
+        double t = 0.0;
+        rc = probe(widths, bpc, &t);
+        if (rc == SW_OK && t < top) {
+            top = t;
+            top_bpc = bpc;
+        }
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    (void)hipGetLastError();
+    if (rc)
+        return rc;
+    for (int i = 0; i < n_problems; ++i)
+        if (!problems[i].width)
+            problems[i].width = widths[i];
+    best->blocks_per_cu = top_bpc;
+    best->reserved0 = 0;
+    best->wait_limit_us = 0;
+    if (best_ms_per_update)
+        *best_ms_per_update = work > 0.0 ? top / work : 0.0;
+    return ok();
 }
 
 } // extern "C"

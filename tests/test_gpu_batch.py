@@ -172,6 +172,17 @@ def test_autotune_records_and_is_used():
     w, threads, ms = sw.sw_autotune(sw.HEAT_F64, n, 0)
     assert w % 64 == 0 and n % w == 0 and n // w >= 2 and threads in (64, 128, 256) and ms > 0
     assert sw.sw_tuned_width(sw.HEAT_F64, n) == (w, threads)
+    # a cell count of the same size class with no record of its own takes it
+    import torch
+    n2 = n + n // 4
+    t2 = torch.zeros(1, n2, dtype=torch.float64, device="cuda")
+    b = sw.Batch([dict(eq=sw.HEAT_F64, width=0, n_cells=n2, n_steps=1, dt=0.25, dx=1.0,
+                       d_state=t2.data_ptr())])
+    if n2 % w == 0 and n2 // w >= 2:
+        assert b.width(0) == w
+    else:
+        assert b.width(0) == sw.sw_default_width(sw.HEAT_F64, n2)
+    b.close()
     u0 = heat_ic(n, 41)
     got = run(sw.HEAT_F64, pack(sw.HEAT_F64, u0), 333, 0.25, 1.0, "swept")[0]
     assert np.array_equal(got, oracle.heat_f64(u0, 333, 0.25))
@@ -198,3 +209,35 @@ def test_autotune_cache_file_persists_across_processes():
         assert b.returncode == 0, b.stderr
         assert a.stdout.strip() == b.stdout.strip()
         assert open(path).read().split()[0].startswith("gfx")
+
+
+def test_batch_autotune_picks_widths_and_workgroups_reading_states_only():
+    """sw_batch_autotune writes a valid width into every problem given with
+    width 0, picks a resident-workgroup count, leaves the caller's states as
+    they were, and a batch built with its choices still matches the
+    individual solves."""
+    import torch
+    specs = [(sw.HEAT_F64, 256 * 5, 40, 0, 51), (sw.HEAT_F64, 256 * 6, 40, 0, 52),
+             (sw.EULER_F32, 256 * 8, 12, 0, 53), (sw.EULER_F32, 256 * 12, 12, 64, 54),
+             (sw.EULER_F64_FLAT, 256 * 8, 9, 0, 55)]
+    tensors, hosts, probs = _problems(specs)
+    announce("batch autotune")
+    bpc, ms = sw.sw_batch_autotune(probs, 8)
+    assert bpc >= 0 and ms > 0
+    for t, h in zip(tensors, hosts):
+        assert np.array_equal(t.cpu().numpy(), h)  # read only
+    assert probs[3]["width"] == 64  # a width given by the caller is kept
+    for p in probs:
+        w = p["width"]
+        step = 2 * sw.radius(p["eq"])
+        assert w > 0 and w % step == 0 and p["n_cells"] % w == 0 and p["n_cells"] // w >= 2
+    b = sw.Batch(probs, blocks_per_cu=bpc)
+    stream = torch.cuda.current_stream().cuda_stream
+    b.run(stream)
+    assert b.wait(stream) == sw.SW_OK, sw.last_error()
+    for i, ((eq, n, steps, width, seed), t, host) in enumerate(zip(specs, tensors, hosts)):
+        assert b.width(i) == probs[i]["width"]
+        dt, dx = _coef(eq)
+        alone = run(eq, host, steps, dt, dx, "swept", width=b.width(i))
+        assert np.array_equal(t.cpu().numpy(), alone), i
+    b.close()

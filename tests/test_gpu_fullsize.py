@@ -139,7 +139,8 @@ def test_euler_f32_n16777216_20000_steps_error_vs_f64():
                                               (sw.HEAT_F32, sw.EULER_F32)])
 def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
     """The batched workload at full size: 4096 problems, lengths log-uniform in
-    [2^10, 2^18], half heat / half Euler, 5000 steps, one persistent launch.
+    [2^10, 2^18], half heat / half Euler, 5000 steps, one persistent launch
+    with widths and resident workgroups per CU from the batch autotuner.
     Every problem must equal its individual swept solve; the 16 smallest are
     also checked against the oracle."""
     import torch
@@ -155,8 +156,10 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
         specs.append(dict(eq=eq, width=0, n_cells=p.n, n_steps=5000, dt=dt, dx=dx,
                           d_state=t.data_ptr()))
     torch.cuda.synchronize()
-    announce("fullsize batch", eq_heat, eq_euler, "problems", len(specs))
-    b = sw.Batch(specs)
+    announce("fullsize batch autotune", eq_heat, eq_euler, "problems", len(specs))
+    bpc, probe_ms = sw.sw_batch_autotune(specs, 300)
+    announce("fullsize batch", eq_heat, eq_euler, "problems", len(specs), "blocks/CU", bpc)
+    b = sw.Batch(specs, blocks_per_cu=bpc)
     stream = torch.cuda.current_stream().cuda_stream
     b.run(stream)
     assert b.wait(stream) == sw.SW_OK, sw.last_error()
@@ -188,5 +191,6 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
     ms = start.elapsed_time(stop)
     cells = sum(p.n for p in probs)
     record(f"batch_4096x5000_{'f64' if sw.is_f64(eq_heat) else 'f32'}", ms=ms, cells=cells,
-           cell_updates_per_s=cells * 5000 / (ms * 1e-3))
+           cell_updates_per_s=cells * 5000 / (ms * 1e-3), blocks_per_cu=bpc,
+           distinct_widths=len(set(widths)), widest=max(widths), narrowest=min(widths))
     b.close()
