@@ -127,8 +127,22 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_persistent(BatchTables 
             switch (P.eq) {
             case 0: heat_f64_tile<kBatchThreads>(jb, lds); break;
             case 1: heat_f32_tile<kBatchThreads>(jb, (float *)lds); break;
-            case 2: euler_f64_tile<kBatchThreads>(jb, lds); break;
-            case 3: euler_f32_tile<kBatchThreads>(jb, lds); break;
+            case 2:  // compile-time LDS offsets for the common Euler widths
+                if (P.w == 512)
+                    euler_f64_tile<kBatchThreads, 512>(jb, lds);
+                else if (P.w == 256)
+                    euler_f64_tile<kBatchThreads, 256>(jb, lds);
+                else
+                    euler_f64_tile<kBatchThreads>(jb, lds);
+                break;
+            case 3:
+                if (P.w == 512)
+                    euler_f32_tile<kBatchThreads, 512>(jb, lds);
+                else if (P.w == 256)
+                    euler_f32_tile<kBatchThreads, 256>(jb, lds);
+                else
+                    euler_f32_tile<kBatchThreads>(jb, lds);
+                break;
             case 4: flat_f64_tile<kBatchThreads>(jb, lds); break;
             default: flat_f32_tile<kBatchThreads>(jb, lds); break;
             }
