@@ -57,6 +57,7 @@ def test_width_limits():
         assert wmax <= 8192
     assert sw.sw_default_width(sw.HEAT_F64, 1 << 22) == 1024
     assert sw.sw_default_width(sw.EULER_F64, 1 << 22) == 512
+    assert sw.sw_default_width(sw.HEAT_F32, 1 << 24) == 2048
     assert sw.sw_default_width(sw.HEAT_F64, 1000) == 500  # largest even divisor with n/W >= 2
     assert sw.sw_default_width(sw.HEAT_F64, 1001) == 0    # odd: no even divisor
     assert sw.sw_default_width(sw.HEAT_F64, 6) == 2
