@@ -127,9 +127,11 @@ size_t sw_workspace_bytes(int eq, int64_t n_cells, int width, int method);
  * 160 KiB of LDS of one gfx950 compute unit).  0 for an invalid eq. */
 int sw_max_width(int eq);
 
-/* The width swept_solve picks when none is given: the largest even divisor
- * of n_cells not above the preferred width for `eq` with n_cells / W >= 2.
- * 0 when there is none. */
+/* The width swept_solve picks when none is given and the autotuner has
+ * recorded none (see sw_tuned_width): the largest valid width (a multiple of
+ * 2R dividing n_cells with n_cells / W >= 2) not above the preferred width
+ * of `eq` -- heat binary64 1024, heat binary32 2048, lengthened Euler 512,
+ * flattened Euler 256, measured on MI355X.  0 when there is none. */
 int sw_default_width(int eq, int64_t n_cells);
 
 /* Swept-rule solve (Sec. 4.1).  Advances d_state by n_steps time steps.
