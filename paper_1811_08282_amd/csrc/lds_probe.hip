@@ -11,6 +11,9 @@
 //           pattern of one heat level in LDS
 //   pair    each thread updates two adjacent cells: a 16-byte read of the
 //           pair, two 8-byte neighbour reads, one 16-byte write
+// and, for the neighbour exchange across lanes instead of through LDS, the
+// rate of 32-bit lane moves each followed by a dependent add: DPP row shift
+// (row_shr:1), DPP whole-wave shift (wave_shr:1) and ds_bpermute.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -94,6 +97,57 @@ __global__ void __launch_bounds__(kThreads) k_probe(double *out, double seed)
     out[(size_t)blockIdx.x * kThreads + tid] = acc0 + acc1;
 }
 
+enum Move { kRowShr, kWaveShr, kPermute, kMoves };
+
+template <int M>
+__global__ void __launch_bounds__(kThreads) k_moves(int *out, int seed)
+{
+    int a = (int)threadIdx.x + seed, b = a * 3 + 1, c = a ^ 0x55, d = a + 7;
+    const int lane = threadIdx.x & 63;
+    const int from = (lane == 0 ? 63 : lane - 1) * 4;  // byte address of lane - 1
+#pragma unroll 8
+    for (int k = 0; k < kIter; ++k) {
+        if (M == kRowShr) {
+            a = __builtin_amdgcn_mov_dpp(a, 0x111, 0xf, 0xf, true) + 1;
+            b = __builtin_amdgcn_mov_dpp(b, 0x111, 0xf, 0xf, true) + 1;
+            c = __builtin_amdgcn_mov_dpp(c, 0x111, 0xf, 0xf, true) + 1;
+            d = __builtin_amdgcn_mov_dpp(d, 0x111, 0xf, 0xf, true) + 1;
+        } else if (M == kWaveShr) {
+            a = __builtin_amdgcn_mov_dpp(a, 0x138, 0xf, 0xf, true) + 1;
+            b = __builtin_amdgcn_mov_dpp(b, 0x138, 0xf, 0xf, true) + 1;
+            c = __builtin_amdgcn_mov_dpp(c, 0x138, 0xf, 0xf, true) + 1;
+            d = __builtin_amdgcn_mov_dpp(d, 0x138, 0xf, 0xf, true) + 1;
+        } else {
+            a = __builtin_amdgcn_ds_bpermute(from, a) + 1;
+            b = __builtin_amdgcn_ds_bpermute(from, b) + 1;
+            c = __builtin_amdgcn_ds_bpermute(from, c) + 1;
+            d = __builtin_amdgcn_ds_bpermute(from, d) + 1;
+        }
+    }
+    out[(size_t)blockIdx.x * kThreads + threadIdx.x] = a + b + c + d;
+}
+
+template <int M>
+float time_moves(int blocks, int *d)
+{
+    hipEvent_t a, b;
+    CHECK(hipEventCreate(&a));
+    CHECK(hipEventCreate(&b));
+    hipLaunchKernelGGL(k_moves<M>, dim3(blocks), dim3(kThreads), 0, 0, d, 1);
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(a, 0));
+    for (int r = 0; r < 5; ++r)
+        hipLaunchKernelGGL(k_moves<M>, dim3(blocks), dim3(kThreads), 0, 0, d, 1);
+    CHECK(hipEventRecord(b, 0));
+    CHECK(hipEventSynchronize(b));
+    float ms = 0.0f;
+    CHECK(hipEventElapsedTime(&ms, a, b));
+    CHECK(hipEventDestroy(a));
+    CHECK(hipEventDestroy(b));
+    return ms / 5.0f;
+}
+
 template <int P>
 float time_pattern(int blocks, double *d)
 {
@@ -146,6 +200,18 @@ int main()
                 lv / (ms[kLevel] * 1e-3), lv / (ms[kLevel] * 1e-3) / clk);
     std::printf("%-10s %8.3f ms  %.3e cell-updates/s  %5.2f per clk per CU\n", "pair", ms[kPair],
                 pr / (ms[kPair] * 1e-3), pr / (ms[kPair] * 1e-3) / clk);
+    int *di = nullptr;
+    CHECK(hipMalloc(&di, sizeof(int) * (size_t)blocks * kThreads));
+    const char *mnames[] = {"row_shr", "wave_shr", "bpermute"};
+    float mms[kMoves];
+    mms[kRowShr] = time_moves<kRowShr>(blocks, di);
+    mms[kWaveShr] = time_moves<kWaveShr>(blocks, di);
+    mms[kPermute] = time_moves<kPermute>(blocks, di);
+    const double moves = (double)blocks * (kThreads / 64) * kIter * 4;  // wave-level moves
+    for (int m = 0; m < kMoves; ++m)
+        std::printf("%-10s %8.3f ms  %5.3f wave moves (+ add) per clk per CU\n", mnames[m], mms[m],
+                    moves / (mms[m] * 1e-3) / clk);
+    CHECK(hipFree(di));
     CHECK(hipFree(d));
     return 0;
 }
