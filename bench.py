@@ -381,6 +381,11 @@ def main() -> int:
         roofline["lds"] = {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                            "frac": lds_gbs / LDS_PEAK_GBS,
                            "bytes_per_cell_update": LDS_BYTES_PER_UPDATE[eq]}
+    # the unit that binds the kernel, from the counter profile and the LDS
+    # probe: the heat level sweep saturates the LDS port (its measured
+    # pattern ceiling is 3.39 updates per clock per CU), the Euler kernels
+    # the VALU issue (correctly rounded divisions and square roots)
+    roofline["binding_unit"] = "lds" if eq in LDS_BYTES_PER_UPDATE else "valu"
     if counters and counters.get("valu_insts_per_launch"):
         # wave-level VALU instructions issued per second over the chip's issue
         # rate (one wave instruction per clock per CU)
