@@ -57,13 +57,23 @@ _lib = None
 
 
 def load() -> ctypes.CDLL:
-    """Load ``libswept.so`` (raises if it has not been built)."""
+    """Load ``libswept.so`` (raises if it has not been built).
+
+    torch ships its own HIP runtime.  If the library were opened first, it
+    would bind to the system HIP runtime and torch, imported later, would
+    load its own: two runtimes on one GPU in one process, neither knowing the
+    other's allocations.  So torch (when installed) is imported first; the
+    library then binds to the runtime torch already loaded."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             f"{LIB_PATH} is missing: build it with `python -m paper_1811_08282_amd.build`")
+    try:
+        import torch  # noqa: F401  (loads torch's HIP runtime before the library)
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     i64, i32, d, vp, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
     solve_args = [i32, i64, i64, d, d, vp, vp]

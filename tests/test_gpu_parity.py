@@ -229,3 +229,36 @@ def test_euler_flat_f32_matches_f32_oracle_bitexact(width):
     nv = run(sw.EULER_F32_FLAT, pack(sw.EULER_F32, q0), steps, 0.1, 1.0, "naive")
     assert np.array_equal(nv[:3], want_q) and np.array_equal(nv[3:], want_c)
     assert np.array_equal(swp, nv)
+
+
+@pytest.mark.parametrize("eq", [sw.HEAT_F64, sw.HEAT_F32, sw.EULER_F64, sw.EULER_F32,
+                                sw.EULER_F64_FLAT, sw.EULER_F32_FLAT])
+def test_widest_tile_of_every_equation(eq):
+    """The largest width the LDS allows (close to the 160 KiB of one CU for
+    Euler), two tiles, enough steps for at least three phases: swept equals
+    the classic path and the oracle of the same precision bit for bit."""
+    w = sw.sw_max_width(eq)
+    n = 2 * w
+    half = w // (2 * sw.radius(eq))
+    steps = (2 * half + 2 + sw.substeps(eq) - 1) // sw.substeps(eq) + 3
+    announce("widest tile", eq, w, steps)
+    if eq in (sw.HEAT_F64, sw.HEAT_F32):
+        q0 = heat_ic(n, 12)
+        dt, dx = 0.25, 1.0
+    else:
+        q0 = sod_tiled(n, n)
+        dt, dx = 0.1, 1.0
+    layout = {sw.EULER_F64_FLAT: sw.EULER_F64, sw.EULER_F32_FLAT: sw.EULER_F32}.get(eq, eq)
+    host = pack(layout, q0)
+    swept = run(eq, host, steps, dt, dx, "swept", width=w)
+    naive = run(eq, host, steps, dt, dx, "naive")
+    assert np.array_equal(swept, naive)
+    if eq == sw.HEAT_F64:
+        want = oracle.heat_f64(host[0], steps, dt / dx ** 2).reshape(1, -1)
+    elif eq == sw.HEAT_F32:
+        want = np.stack(oracle.heat_f32(host[0], host[1], steps, dt / dx ** 2))
+    elif eq in (sw.EULER_F64, sw.EULER_F64_FLAT):
+        want = oracle.euler_f64(host, steps, dt / dx)
+    else:
+        want = np.concatenate(oracle.euler_f32(host[:3], host[3:], steps, dt / dx))
+    assert np.array_equal(swept, want)
