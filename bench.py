@@ -381,6 +381,15 @@ def main() -> int:
         roofline["lds"] = {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                            "frac": lds_gbs / LDS_PEAK_GBS,
                            "bytes_per_cell_update": LDS_BYTES_PER_UPDATE[eq]}
+    if counters and counters.get("lds_load_bytes_per_launch") is not None:
+        # LDS bytes the SQ counters saw (64-byte units of the load and store
+        # bandwidth counters), per cell-update and per second of launch time
+        lds_bytes = counters["lds_load_bytes_per_launch"] + counters["lds_store_bytes_per_launch"]
+        measured = {"bytes_per_cell_update": lds_bytes / (updates / phases),
+                    "achieved": lds_bytes / (launch_ms * 1e-3) / 1e9, "peak": LDS_PEAK_GBS,
+                    "unit": "GB/s"}
+        measured["frac"] = measured["achieved"] / LDS_PEAK_GBS
+        roofline.setdefault("lds", {})["measured"] = measured
     # the unit that binds the kernel, from the counter profile and the LDS
     # probe: the heat level sweep saturates the LDS port (its measured
     # pattern ceiling is 3.39 updates per clock per CU), the Euler kernels
