@@ -22,8 +22,8 @@ constexpr int kStructBytesFlatF32 = 36;   // Q0[3], c[3], Q1[3] (f32)
 // LDS bytes per tile cell of each swept kernel (struct + scratch).
 constexpr int kLdsPerCellHeatF64 = 16;
 constexpr int kLdsPerCellHeatF32 = 12;
-constexpr int kLdsPerCellEulerF64 = 88;  // struct 56 + pressure 8 + face flux 24
-constexpr int kLdsPerCellEulerF32 = 64;  // struct 44 + pressure 8 + face flux 12
+constexpr int kLdsPerCellEulerF64 = 64;  // struct 56 + pressure 8
+constexpr int kLdsPerCellEulerF32 = 52;  // struct 44 + pressure 8
 constexpr int kLdsPerCellFlatF64 = 88;   // struct 48 + pressure, ratio 16 + face flux 24
 constexpr int kLdsPerCellFlatF32 = 64;   // struct 36 + pressure, ratio 16 + face flux 12
 

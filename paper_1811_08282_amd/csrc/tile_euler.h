@@ -19,10 +19,14 @@
 // needs (Pr is written only at sub-steps 0/2, Q1 at 1, Q0 at 3), which is why
 // one struct per cell carries both of its latest levels.
 //
-// Face sharing: inside a level every face flux is computed once into LDS and
-// used by both cells it separates.  Each cell's pressure is kept in LDS and
-// refreshed whenever its state changes, so a ratio sub-step reads three
-// stored pressures instead of recomputing them.
+// Face sharing: inside a flux sub-step every face flux is computed once and
+// used by both cells it separates, without going through LDS: each lane
+// evaluates the face on the left of its cell and takes the face on the right
+// from the next lane (a DPP lane shift), so a wave updates 63 cells and its
+// last lane only evaluates the face the 63rd cell needs.  The sub-step then
+// needs one barrier (after the update) instead of two.  Each cell's pressure
+// is kept in LDS and refreshed whenever its state changes, so a ratio
+// sub-step reads three stored pressures instead of recomputing them.
 #pragma once
 
 #include <math.h>
@@ -46,6 +50,22 @@ __device__ __forceinline__ double ratio(double pm, double pc, double pp)
 {
     return (pp - pc) / (pc - pm);
 }
+
+// lane l receives v of lane l+1 (lane 63 receives 0)
+__device__ __forceinline__ double from_next_lane(double v)
+{
+    const long long vi = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)vi, 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(vi >> 32), 0x130, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ float from_next_lane(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+constexpr int kFaceLanes = 63;  // cells a wave updates per pass (lane 63: face only)
 
 // ---- binary64 ----------------------------------------------------------------
 
@@ -93,7 +113,7 @@ __device__ __forceinline__ int64_t entry_level(const TileJob &jb, int i, int w)
     return lv < cap ? lv : cap;
 }
 
-// LDS: q0[3][wp] q1[3][wp] pr[wp] P[wp] tmp[3][wp]   (doubles, wp = w + 2)
+// LDS: q0[3][wp] q1[3][wp] pr[wp] P[wp]   (doubles, wp = w + 2)
 // P holds the pressure of the state the next ratio sub-step reads: p(Q0) for
 // a cell whose level is 0 or 1 mod 4, p(Q1) for 2 or 3 mod 4.  It is set
 // from the entry level at load and refreshed by every predictor/corrector.
@@ -102,16 +122,18 @@ __device__ __forceinline__ void euler_f64_tile(const TileJob &jb, double *lds)
 {
     const int w = WT > 0 ? WT : jb.w;  // compile-time width when WT > 0
     const int wp = w + 2;
+    constexpr int kWaves = NT / 64;
     const int64_t n = jb.n;
     double *q0 = lds;
     double *q1 = lds + 3 * wp;
     double *pr = lds + 6 * wp;
     double *pp = lds + 7 * wp;
-    double *tmp = lds + 8 * wp;
     double *state = (double *)jb.state;
     const double *ws_in = (const double *)jb.ws_in;
     double *ws_out = (double *)jb.ws_out;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid) >> 6;
 
     for (int i = tid; i < wp; i += NT) {
         const int64_t g = wrap_cell(jb.g0 + i, n);
@@ -137,26 +159,34 @@ __device__ __forceinline__ void euler_f64_tile(const TileJob &jb, double *lds)
         if ((t & 1) == 0) {
             for (int i = lo + tid; i < hi; i += NT)
                 pr[i] = ratio(pp[i - 1], pp[i], pp[i + 1]);
-            __syncthreads();
         } else {
+            // predictor (t = 1) reads Q0 and writes Q1, corrector (t = 3)
+            // reads Q1 and updates Q0: no lane reads what another writes
             const double *q = (t == 1) ? q0 : q1;
-            // tmp[k][i]: flux through the face between LDS cells i-1 and i
-            for (int i = lo + tid; i < hi + 1; i += NT)
-                face64(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
-                       pr[i - 1], pr[i], tmp[i], tmp[wp + i], tmp[2 * wp + i]);
-            __syncthreads();
             double *dst = (t == 1) ? q1 : q0;
             const double c = (t == 1) ? half_lam : lam;
-            for (int i = lo + tid; i < hi; i += NT) {
-                double nq[3];
-                for (int k = 0; k < 3; ++k)
-                    nq[k] = q0[k * wp + i] + c * (tmp[k * wp + i] - tmp[k * wp + i + 1]);
-                for (int k = 0; k < 3; ++k)
-                    dst[k * wp + i] = nq[k];
-                pp[i] = pressure64(nq[0], nq[1], nq[2]);
+            const int chunks = (hi - lo + kFaceLanes - 1) / kFaceLanes;
+            for (int k = wave; k < chunks; k += kWaves) {
+                const int cell = lo + kFaceLanes * k + lane;
+                const int i = cell < hi ? cell : hi;  // face between LDS cells i-1 and i
+                double f0, f1, f2;
+                face64(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
+                       pr[i - 1], pr[i], f0, f1, f2);
+                const double g0 = from_next_lane(f0);
+                const double g1 = from_next_lane(f1);
+                const double g2 = from_next_lane(f2);
+                if (lane < kFaceLanes && cell < hi) {
+                    const double n0 = q0[cell] + c * (f0 - g0);
+                    const double n1 = q0[wp + cell] + c * (f1 - g1);
+                    const double n2 = q0[2 * wp + cell] + c * (f2 - g2);
+                    dst[cell] = n0;
+                    dst[wp + cell] = n1;
+                    dst[2 * wp + cell] = n2;
+                    pp[cell] = pressure64(n0, n1, n2);
+                }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
 
     for (int i = 1 + tid; i <= w; i += NT) {
@@ -213,18 +243,18 @@ __device__ __forceinline__ float kahan_add(float q, float d, float &c)
     return t;
 }
 
-// LDS: pr[wp], P[wp] (double), tmp[3][wp], q0[3][wp], c[3][wp], q1[3][wp] (float).
+// LDS: pr[wp], P[wp] (double), q0[3][wp], c[3][wp], q1[3][wp] (float).
 // ws layout: q0[3][n], c[3][n], q1[3][n] floats, then pr[n] doubles at byte 36n.
 template <int NT, int WT = 0>
 __device__ __forceinline__ void euler_f32_tile(const TileJob &jb, double *ldsd)
 {
     const int w = WT > 0 ? WT : jb.w;  // compile-time width when WT > 0
     const int wp = w + 2;
+    constexpr int kWaves = NT / 64;
     const int64_t n = jb.n;
     double *pr = ldsd;
     double *pp = ldsd + wp;
-    float *ftmp = (float *)(ldsd + 2 * wp);
-    float *fst = ftmp + 3 * wp;  // q0[3], c[3], q1[3]
+    float *fst = (float *)(ldsd + 2 * wp);  // q0[3], c[3], q1[3]
     float *q0 = fst;
     float *cc = fst + 3 * wp;
     float *q1 = fst + 6 * wp;
@@ -234,6 +264,8 @@ __device__ __forceinline__ void euler_f32_tile(const TileJob &jb, double *ldsd)
     float *wout = (float *)jb.ws_out;
     double *wout_pr = (double *)((char *)jb.ws_out + 36 * n);
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid) >> 6;
 
     for (int i = tid; i < wp; i += NT) {
         const int64_t g = wrap_cell(jb.g0 + i, n);
@@ -260,39 +292,39 @@ __device__ __forceinline__ void euler_f32_tile(const TileJob &jb, double *ldsd)
         if ((t & 1) == 0) {
             for (int i = lo + tid; i < hi; i += NT)
                 pr[i] = ratio(pp[i - 1], pp[i], pp[i + 1]);
-            __syncthreads();
         } else {
             const float *q = (t == 1) ? q0 : q1;
-            for (int i = lo + tid; i < hi + 1; i += NT)
+            const int chunks = (hi - lo + kFaceLanes - 1) / kFaceLanes;
+            for (int k = wave; k < chunks; k += kWaves) {
+                const int cell = lo + kFaceLanes * k + lane;
+                const int i = cell < hi ? cell : hi;
+                float f0, f1, f2;
                 face32(q[i - 1], q[wp + i - 1], q[2 * wp + i - 1], q[i], q[wp + i], q[2 * wp + i],
-                       pr[i - 1], pr[i], ftmp[i], ftmp[wp + i], ftmp[2 * wp + i]);
-            __syncthreads();
-            if (t == 1) {
-                for (int i = lo + tid; i < hi; i += NT) {
+                       pr[i - 1], pr[i], f0, f1, f2);
+                const float g0 = from_next_lane(f0);
+                const float g1 = from_next_lane(f1);
+                const float g2 = from_next_lane(f2);
+                if (lane < kFaceLanes && cell < hi) {
                     float nq[3];
-                    for (int k = 0; k < 3; ++k)
-                        nq[k] = q0[k * wp + i] +
-                                half_lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]);
-                    for (int k = 0; k < 3; ++k)
-                        q1[k * wp + i] = nq[k];
-                    pp[i] = pressure32(nq[0], nq[1], nq[2]);
-                }
-            } else {
-                for (int i = lo + tid; i < hi; i += NT) {
-                    float nq[3];
-                    for (int k = 0; k < 3; ++k) {
-                        float c = cc[k * wp + i];
-                        nq[k] = kahan_add(q0[k * wp + i],
-                                          lam * (ftmp[k * wp + i] - ftmp[k * wp + i + 1]), c);
-                        cc[k * wp + i] = c;
+                    const float f[3] = {f0, f1, f2}, gg[3] = {g0, g1, g2};
+                    if (t == 1) {
+                        for (int m = 0; m < 3; ++m) {
+                            nq[m] = q0[m * wp + cell] + half_lam * (f[m] - gg[m]);
+                            q1[m * wp + cell] = nq[m];
+                        }
+                    } else {
+                        for (int m = 0; m < 3; ++m) {
+                            float comp = cc[m * wp + cell];
+                            nq[m] = kahan_add(q0[m * wp + cell], lam * (f[m] - gg[m]), comp);
+                            cc[m * wp + cell] = comp;
+                            q0[m * wp + cell] = nq[m];
+                        }
                     }
-                    for (int k = 0; k < 3; ++k)
-                        q0[k * wp + i] = nq[k];
-                    pp[i] = pressure32(nq[0], nq[1], nq[2]);
+                    pp[cell] = pressure32(nq[0], nq[1], nq[2]);
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
 
     for (int i = 1 + tid; i <= w; i += NT) {

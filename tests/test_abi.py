@@ -49,8 +49,8 @@ def test_state_and_workspace_sizes():
 
 
 def test_width_limits():
-    for eq, per_cell, rad in ((sw.HEAT_F64, 16, 1), (sw.HEAT_F32, 12, 1), (sw.EULER_F64, 88, 1),
-                              (sw.EULER_F32, 64, 1), (sw.EULER_F64_FLAT, 88, 2),
+    for eq, per_cell, rad in ((sw.HEAT_F64, 16, 1), (sw.HEAT_F32, 12, 1), (sw.EULER_F64, 64, 1),
+                              (sw.EULER_F32, 52, 1), (sw.EULER_F64_FLAT, 88, 2),
                               (sw.EULER_F32_FLAT, 64, 2)):
         wmax = sw.sw_max_width(eq)
         assert wmax % (2 * rad) == 0 and (wmax + 2 * rad) * per_cell <= 160 * 1024
