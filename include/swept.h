@@ -131,7 +131,7 @@ int sw_max_width(int eq);
  * recorded none (see sw_tuned_width): the largest valid width (a multiple of
  * 2R dividing n_cells with n_cells / W >= 2) not above the preferred width
  * of `eq` -- heat binary64 1024, heat binary32 2048, lengthened Euler 512,
- * flattened Euler 256, measured on MI355X.  0 when there is none. */
+ * flattened Euler 1024, measured on MI355X.  0 when there is none. */
 int sw_default_width(int eq, int64_t n_cells);
 
 /* Swept-rule solve (Sec. 4.1).  Advances d_state by n_steps time steps.

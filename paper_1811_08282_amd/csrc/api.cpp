@@ -76,14 +76,14 @@ int struct_bytes(int eq)
 
 // measured on MI355X with 256-thread workgroups: heat binary64 best at 1024
 // (2^22 cells), heat binary32 at 2048 (2^24 cells), lengthened Euler at 512,
-// flattened Euler at 256; sw_autotune refines per grid size
+// flattened Euler at 1024; sw_autotune refines per grid size
 int preferred_width(int eq)
 {
     if (eq == SW_HEAT_F32)
         return 2048;
     if (!is_euler(eq))
         return 1024;
-    return is_flat(eq) ? 256 : 512;
+    return is_flat(eq) ? 1024 : 512;
 }
 
 

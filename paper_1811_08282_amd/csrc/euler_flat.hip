@@ -146,6 +146,9 @@ hipError_t flat_f64_swept_phase(const PhaseLaunch &p, double *state, const doubl
         case 512: return launch_kernel(k_flat_f64_phase<256, 512>, g, 256, lds, s,
             state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
             (int)p.first, (int)p.last);
+        case 1024: return launch_kernel(k_flat_f64_phase<256, 1024>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
         default: break;
         }
     }
@@ -165,6 +168,9 @@ hipError_t flat_f32_swept_phase(const PhaseLaunch &p, float *state, const float 
             state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
             (int)p.first, (int)p.last);
         case 512: return launch_kernel(k_flat_f32_phase<256, 512>, g, 256, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        case 1024: return launch_kernel(k_flat_f32_phase<256, 1024>, g, 256, lds, s,
             state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
             (int)p.first, (int)p.last);
         default: break;

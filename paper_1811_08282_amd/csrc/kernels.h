@@ -24,8 +24,8 @@ constexpr int kLdsPerCellHeatF64 = 16;
 constexpr int kLdsPerCellHeatF32 = 12;
 constexpr int kLdsPerCellEulerF64 = 64;  // struct 56 + pressure 8
 constexpr int kLdsPerCellEulerF32 = 52;  // struct 44 + pressure 8
-constexpr int kLdsPerCellFlatF64 = 88;   // struct 48 + pressure, ratio 16 + face flux 24
-constexpr int kLdsPerCellFlatF32 = 64;   // struct 36 + pressure, ratio 16 + face flux 12
+constexpr int kLdsPerCellFlatF64 = 48;   // struct only: pressures, ratios, fluxes by lane shifts
+constexpr int kLdsPerCellFlatF32 = 36;   // struct only
 
 // Description of one swept phase launch.
 struct PhaseLaunch {

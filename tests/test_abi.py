@@ -50,8 +50,8 @@ def test_state_and_workspace_sizes():
 
 def test_width_limits():
     for eq, per_cell, rad in ((sw.HEAT_F64, 16, 1), (sw.HEAT_F32, 12, 1), (sw.EULER_F64, 64, 1),
-                              (sw.EULER_F32, 52, 1), (sw.EULER_F64_FLAT, 88, 2),
-                              (sw.EULER_F32_FLAT, 64, 2)):
+                              (sw.EULER_F32, 52, 1), (sw.EULER_F64_FLAT, 48, 2),
+                              (sw.EULER_F32_FLAT, 36, 2)):
         wmax = sw.sw_max_width(eq)
         assert wmax % (2 * rad) == 0 and (wmax + 2 * rad) * per_cell <= 160 * 1024
         assert wmax <= 8192
@@ -62,7 +62,7 @@ def test_width_limits():
     assert sw.sw_default_width(sw.HEAT_F64, 1001) == 0    # odd: no even divisor
     assert sw.sw_default_width(sw.HEAT_F64, 6) == 2
     # flattened Euler needs widths that are multiples of 4
-    assert sw.sw_default_width(sw.EULER_F64_FLAT, 1 << 22) == 256
+    assert sw.sw_default_width(sw.EULER_F64_FLAT, 1 << 22) == 1024
     assert sw.sw_default_width(sw.EULER_F64_FLAT, 24) == 12
     assert sw.sw_default_width(sw.EULER_F64_FLAT, 18) == 0
 
