@@ -94,7 +94,8 @@ def measured_counters(work, eq, width):
     """Per-launch hardware counters of the swept phase kernel taken with
     rocprofv3 on this workload (profiles/<workload>_phase_counters.txt), or None when
     absent or taken on other kernel sources or another width."""
-    path = os.path.join(PROFILES, f"{work.name}_phase_counters.txt")
+    layout = "_flattened" if eq in (sw.EULER_F64_FLAT, sw.EULER_F32_FLAT) else ""
+    path = os.path.join(PROFILES, f"{work.name}{layout}_phase_counters.txt")
     if not os.path.exists(path):
         return None
     with open(path) as f:
