@@ -241,3 +241,34 @@ def test_batch_autotune_picks_widths_and_workgroups_reading_states_only():
         alone = run(eq, host, steps, dt, dx, "swept", width=b.width(i))
         assert np.array_equal(t.cpu().numpy(), alone), i
     b.close()
+
+
+@pytest.mark.parametrize("eq", [sw.HEAT_F64, sw.EULER_F64, sw.EULER_F32_FLAT])
+def test_swept_solve_captured_in_a_graph(eq):
+    """swept_solve_ex with a caller workspace captured into a HIP graph: three
+    replays, with eager solves and host synchronisation between them, each
+    equal to the same number of eager solves."""
+    import torch
+    n, steps = 4096, 150
+    if eq == sw.HEAT_F64:
+        host, dt = pack(eq, heat_ic(n, 71)), 0.25
+    else:
+        host, dt = pack(_pack_eq(eq), sod_tiled(n, 1024)), 0.1
+    nbytes = sw.sw_workspace_bytes(eq, n)
+    ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
+    assert ws.data_ptr() % 256 == 0
+    state = torch.from_numpy(np.ascontiguousarray(host)).cuda()
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    announce("graph capture", eq)
+    with torch.cuda.graph(graph, stream=stream):
+        sw.solve(eq, state, steps, dt, 1.0, workspace=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(state.cpu().numpy(), host)  # capture runs nothing
+    eager = host.copy()
+    for rep in range(3):
+        announce("graph replay", eq, rep)
+        graph.replay()
+        torch.cuda.synchronize()
+        eager = run(eq, eager, steps, dt, 1.0, "swept")
+        assert np.array_equal(state.cpu().numpy(), eager), rep
