@@ -135,12 +135,16 @@ int sw_max_width(int eq);
 int sw_default_width(int eq, int64_t n_cells);
 
 /* Swept-rule solve (Sec. 4.1).  Advances d_state by n_steps time steps.
- * dt, dx: finite and > 0.  n_steps >= 0 (0 is a no-op).  n_cells >= 4. */
+ * dt, dx: finite and > 0.  n_steps >= 0 (0 is a no-op).  n_cells >= 4.
+ * One phase is one launch of n_cells / W workgroups, which HIP bounds at
+ * 2^32 - 1 work-items: SW_ERR_ARG when (n_cells / W) * workgroup size
+ * exceeds that (a wider tile fixes it). */
 int swept_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
                 void *d_state, sw_stream stream);
 
 /* Classic decomposition: one kernel launch per sub-step (Sec. 4.1, Fig. 2b).
- * Same arguments and result as swept_solve.  n_cells >= 3. */
+ * Same arguments and result as swept_solve.  3 <= n_cells <= 2^32 - 256
+ * (at most one work-item per cell in one launch), else SW_ERR_ARG. */
 int naive_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
                 void *d_state, sw_stream stream);
 
@@ -215,7 +219,7 @@ void sw_tune_clear(void);
 typedef struct {
     int eq;          /* sw_equation                                          */
     int width;       /* triangle width, 0 = tuned width, else library choice */
-    int64_t n_cells; /* >= 4                                                 */
+    int64_t n_cells; /* >= 4; n_cells / width <= 2^31 - 1                     */
     int64_t n_steps; /* >= 0                                                 */
     double dt, dx;   /* finite, > 0                                          */
     void *d_state;   /* device state buffer laid out as for swept_solve; the

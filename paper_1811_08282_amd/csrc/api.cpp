@@ -49,6 +49,8 @@ int radius(int eq) { return is_flat(eq) ? 2 : 1; }
 
 constexpr int64_t kMaxCells = (int64_t)1 << 40;
 constexpr int64_t kMaxWidth = 8192;
+constexpr uint64_t kMaxLaunchItems = 0xFFFFFFFFull;  // work-items of one HIP launch
+constexpr size_t kNaiveGroup = 256;                  // workgroup size of the classic kernels
 
 int lds_per_cell(int eq)
 {
@@ -414,6 +416,19 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
         return fail(SW_ERR_ARG, "threads must be 0, 64, 128 or 256");
     if (o && o->d_workspace && ((uintptr_t)o->d_workspace & 255) != 0)
         return fail(SW_ERR_ARG, "workspace must be 256-byte aligned");
+    const int threads = (o && o->threads) ? o->threads
+                        : (tuned_threads ? tuned_threads : sw::default_phase_threads(w));
+    // a launch holds at most 2^32 - 1 work-items: one workgroup per tile in
+    // a swept phase, at most one work-item per cell in a classic sub-step
+    if (method == SW_METHOD_SWEPT
+            ? (uint64_t)(n / w) * (uint64_t)threads > kMaxLaunchItems
+            : (uint64_t)round_up((size_t)n, kNaiveGroup) > kMaxLaunchItems)
+        return fail(SW_ERR_ARG,
+                    method == SW_METHOD_SWEPT
+                        ? "n_cells %lld in tiles of %d cells needs more than 2^32 work-items in "
+                          "one launch; use a wider tile"
+                        : "n_cells %lld exceeds the classic kernels' limit of 2^32 - 256 cells",
+                    (long long)n, w);
     if (steps == 0)
         return ok();
     int dev = 0;
@@ -427,8 +442,6 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
     rc = get_workspace(dev, s, need, o, &ws);
     if (rc)
         return rc;
-    const int threads = (o && o->threads) ? o->threads
-                        : (tuned_threads ? tuned_threads : sw::default_phase_threads(w));
     rc = (method == SW_METHOD_SWEPT) ? run_swept(eq, n, steps, dt, dx, state, s, w, threads, ws)
                                      : run_naive(eq, n, steps, dt, dx, state, s, ws);
     return rc ? rc : ok();

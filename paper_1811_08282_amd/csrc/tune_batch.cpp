@@ -421,6 +421,9 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
                 return fail(SW_ERR_UNSUPPORTED, "problem %d: no valid width for n_cells %lld", i,
                             (long long)p.n_cells);
         }
+        if (p.n_cells / w > (int64_t)INT32_MAX)
+            return fail(SW_ERR_ARG, "problem %d: %lld tiles of %d cells exceed 2^31 - 1", i,
+                        (long long)(p.n_cells / w), w);
         widths[i] = w;
         sw::BatchProblem &b = hp[i];
         b.state = p.d_state;
@@ -466,8 +469,9 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
     b->array_bytes = array_bytes;
     if (hipMalloc(&b->tables, b->table_bytes) != hipSuccess ||
         (array_bytes && hipMalloc(&b->arrays, array_bytes) != hipSuccess)) {
+        const size_t table_bytes = b->table_bytes;
         free_batch(b);
-        return fail(SW_ERR_NOMEM, "batch allocation of %zu + %zu bytes failed", (size_t)0,
+        return fail(SW_ERR_NOMEM, "batch allocation of %zu + %zu bytes failed", table_bytes,
                     array_bytes);
     }
     char *arr = (char *)b->arrays;

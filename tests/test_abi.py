@@ -121,3 +121,18 @@ def test_python_binding_names_match_c_abi():
                  "sw_phase_count", "sw_phase_info", "sw_phase_interval", "sw_release"):
         assert callable(getattr(sw, name))
     assert ctypes.sizeof(sw.sw_opts) == 24
+
+
+def test_launch_work_item_limit_rejected_on_host():
+    # 2^31 cells in tiles of 64 with 256-thread workgroups: 2^33 work-items in one phase
+    big = 1 << 31
+    rc = sw.swept_solve_ex(sw.HEAT_F64, big, 5, 0.25, 1.0, FAKE, None, width=64, threads=256)
+    assert rc == sw.SW_ERR_ARG and "work-items" in sw.last_error()
+    # the classic kernels launch one work-item per cell
+    assert sw.naive_solve(sw.HEAT_F64, 1 << 33, 5, 0.25, 1.0, FAKE, None) == sw.SW_ERR_ARG
+    assert "2^32" in sw.last_error()
+    assert sw.naive_solve(sw.EULER_F64, (1 << 32) - 255, 0, 0.1, 1.0, FAKE, None) == sw.SW_ERR_ARG
+    # at the edge of the limit the call gets past the launch check (zero steps: no-op)
+    assert sw.naive_solve(sw.EULER_F64, (1 << 32) - 256, 0, 0.1, 1.0, FAKE, None) == sw.SW_OK
+    assert sw.swept_solve_ex(sw.HEAT_F64, big, 0, 0.25, 1.0, FAKE, None, width=2048,
+                             threads=256) == sw.SW_OK
