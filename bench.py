@@ -90,17 +90,18 @@ def kernel_source_hash(eq) -> str:
     return h.hexdigest()
 
 
-def measured_counters(work, eq, width):
+def measured_counters(work, eq, width, threads):
     """Per-launch hardware counters of the swept phase kernel taken with
     rocprofv3 on this workload (profiles/<workload>_phase_counters.txt), or None when
-    absent or taken on other kernel sources or another width."""
+    absent or taken on other kernel sources or another launch (width, workgroup size)."""
     layout = "_flattened" if eq in (sw.EULER_F64_FLAT, sw.EULER_F32_FLAT) else ""
     path = os.path.join(PROFILES, f"{work.name}{layout}_phase_counters.txt")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha256") != kernel_source_hash(eq) or rec.get("width") != width:
+    if (rec.get("source_sha256") != kernel_source_hash(eq) or rec.get("width") != width
+            or rec.get("threads") != threads):
         return None
     return rec
 
@@ -120,19 +121,21 @@ def pack_state(eq, q):
     return np.concatenate([q.astype(np.float32), np.zeros(q.shape, np.float32)])
 
 
-def time_solves(torch, eq, state0, work, method, width, reps, warmup):
+def time_solves(torch, eq, state0, work, method, width, reps, warmup, threads=0):
     """Mean ms per solve over `reps` solves (events on the library's stream)."""
     dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width)
+        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width,
+                 threads=threads)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record(stream)
     t0 = time.perf_counter()
     for _ in range(reps):
-        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width)
+        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width,
+                 threads=threads)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
@@ -305,6 +308,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
     ap.add_argument("--workload", default="heat_f64_large", choices=sorted(WORKLOADS))
     ap.add_argument("--width", type=int, default=0, help="triangle width (0: library choice)")
+    ap.add_argument("--threads", type=int, default=0,
+                    help="workgroup size of the swept phases (0: library choice)")
     ap.add_argument("--naive-reps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -336,13 +341,15 @@ def main() -> int:
     work, eq = WORKLOADS[args.workload]
     sw.load()
     width = args.width or sw.sw_default_width(eq, work.n)
+    threads = args.threads or sw.sw_default_threads(eq, width)
     final_level = work.steps * sw.substeps(eq)
     phases = sw.sw_phase_count(final_level, width, sw.radius(eq))
     state0 = pack_state(eq, wl.initial_state(work))
     updates = work.n * work.steps
 
-    log(f"[bench] workload {work.name} eq={eq} W={width} phases={phases}")
-    ms, wall_ms = time_solves(torch, eq, state0, work, "swept", width, args.steps, args.warmup)
+    log(f"[bench] workload {work.name} eq={eq} W={width} threads={threads} phases={phases}")
+    ms, wall_ms = time_solves(torch, eq, state0, work, "swept", width, args.steps, args.warmup,
+                              threads)
     log(f"[bench] swept {ms:.3f} ms/solve ({updates / ms * 1e3:.4g} cell-updates/s)")
     naive_ms = float("nan")
     if not args.no_naive:
@@ -354,7 +361,7 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
-    sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width)
+    sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width, threads=threads)
     host_final = dev.cpu().numpy()
     paper_ms = (time.perf_counter() - t0) * 1e3
     del dev, host_final
@@ -368,7 +375,7 @@ def main() -> int:
     achieved_gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
     hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes}
-    counters = measured_counters(work, eq, width)
+    counters = measured_counters(work, eq, width, threads)
     traffic = counters.get("hbm_bytes_per_launch") if counters else None
     ops = OPS_PER_UPDATE[eq]
     achieved = value * ops / 1e12
@@ -419,6 +426,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": work.name + ("_flattened" if eq in (sw.EULER_F64_FLAT, sw.EULER_F32_FLAT) else ""),
                    "n_cells": work.n, "time_steps": work.steps, "width": width,
+                   "threads": threads,
                    "method": "swept", "parallelism": "single-gpu"},
         "naive": {"value": naive_value, "ms_per_step": naive_ms,
                   "hbm_roofline_value": HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]},
@@ -434,7 +442,8 @@ def main() -> int:
         # one more solve from the same input, outside the timed region, for
         # the sampled check against the oracle in the CPU leg
         dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
-        sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width)
+        sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width,
+                 threads=threads)
         torch.cuda.synchronize()
         final = dev.cpu().numpy()
         del dev

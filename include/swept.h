@@ -96,9 +96,8 @@ typedef void *sw_stream;
  *                     choice.  Valid W: a multiple of 2R (R = 2 for the
  *                     flattened layout, else 1), W divides n_cells,
  *                     n_cells / W >= 2, W <= sw_max_width(eq).
- *   threads         : workgroup size of the swept phase kernels: 64, 128 or
- *                     256 (0 = library choice: W rounded up to a multiple of
- *                     64, at most 256).
+ *   threads         : workgroup size of the swept phase kernels: 64, 128,
+ *                     256 or 512 (0 = library choice, sw_default_threads).
  *   d_workspace     : device working arrays supplied by the caller (at least
  *                     sw_workspace_bytes() long, 256-byte aligned), or NULL
  *                     for the library's cached arrays.  Required when the
@@ -130,9 +129,16 @@ int sw_max_width(int eq);
 /* The width swept_solve picks when none is given and the autotuner has
  * recorded none (see sw_tuned_width): the largest valid width (a multiple of
  * 2R dividing n_cells with n_cells / W >= 2) not above the preferred width
- * of `eq` -- heat binary64 1024, heat binary32 2048, lengthened Euler 512,
- * flattened Euler 1024, measured on MI355X.  0 when there is none. */
+ * of `eq` -- heat binary64 1024, heat binary32 2048, Euler 1024 (flattened
+ * binary32 2048), measured on MI355X.  0 when there is none. */
 int sw_default_width(int eq, int64_t n_cells);
+
+/* The workgroup size swept_solve uses for tile width `width` when none is
+ * given and the autotuner has recorded none: 512 for Euler tiles of 1024
+ * cells or more (twice the resident waves per compute unit at the same
+ * LDS), else the width rounded up to whole 64-lane waves, at most 256.
+ * 0 for an invalid eq or width. */
+int sw_default_threads(int eq, int width);
 
 /* Swept-rule solve (Sec. 4.1).  Advances d_state by n_steps time steps.
  * dt, dx: finite and > 0.  n_steps >= 0 (0 is a no-op).  n_cells >= 4.
@@ -186,7 +192,7 @@ int sw_phase_interval(int64_t k, int64_t final_level, int width, int radius, int
  * steps before a long run, starting from wide blocks (Sec. 6).  sw_autotune
  * times short swept solves on a scratch state (allocated and freed here) over
  * every valid width that is a multiple of 64 (every valid width if there is
- * none) and workgroup sizes 64/128/256, and records the fastest for
+ * none) and workgroup sizes 64/128/256/512, and records the fastest for
  * (device architecture, eq, n_cells).  swept_solve and the batch use a
  * recorded width whenever the caller gives none.  probe_steps = 0 picks
  * enough steps for four phases at the widest candidate.  If the environment
@@ -215,7 +221,11 @@ void sw_tune_clear(void);
  * swept_solve, and publishes its flag.  Each problem ends bit-identical to
  * swept_solve of that problem with the same width.  Every wait is bounded in
  * time: a wait that exceeds the bound aborts the whole launch, which then
- * reports SW_ERR_HIP from sw_batch_wait. */
+ * reports SW_ERR_HIP from sw_batch_wait.  The persistent kernel runs
+ * 256-thread workgroups; a problem without a width and without a tuned one
+ * takes the largest valid width up to 1024 (heat binary32 2048, lengthened
+ * Euler 512), and the LDS of the widest tile sets the resident workgroups
+ * per CU of the whole batch. */
 typedef struct {
     int eq;          /* sw_equation                                          */
     int width;       /* triangle width, 0 = tuned width, else library choice */

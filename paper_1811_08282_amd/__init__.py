@@ -91,6 +91,8 @@ def load() -> ctypes.CDLL:
     lib.sw_max_width.restype = i32
     lib.sw_default_width.argtypes = [i32, i64]
     lib.sw_default_width.restype = i32
+    lib.sw_default_threads.argtypes = [i32, i32]
+    lib.sw_default_threads.restype = i32
     lib.sw_phase_count.argtypes = [i64, i32, i32]
     lib.sw_phase_count.restype = i64
     lib.sw_phase_info.argtypes = [i64, i64, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -183,6 +185,10 @@ def sw_max_width(eq) -> int:
 
 def sw_default_width(eq, n_cells) -> int:
     return load().sw_default_width(eq, n_cells)
+
+
+def sw_default_threads(eq, width) -> int:
+    return load().sw_default_threads(eq, width)
 
 
 def sw_phase_count(final_level, width, radius=1) -> int:

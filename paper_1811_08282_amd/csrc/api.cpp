@@ -76,16 +76,35 @@ int struct_bytes(int eq)
     }
 }
 
-// measured on MI355X with 256-thread workgroups: heat binary64 best at 1024
-// (2^22 cells), heat binary32 at 2048 (2^24 cells), lengthened Euler at 512,
-// flattened Euler at 1024; sw_autotune refines per grid size
+// measured on MI355X (2^22 cells binary64, 2^24 binary32): heat binary64
+// best at 1024, heat binary32 at 2048, Euler at 1024 with 512-thread
+// workgroups (flattened binary32 equally fast at 2048); sw_autotune refines
+// per grid size
 int preferred_width(int eq)
+{
+    if (eq == SW_HEAT_F32 || eq == SW_EULER_F32_FLAT)
+        return 2048;
+    return 1024;
+}
+
+// the same for the batch kernel, whose workgroups have 256 threads:
+// lengthened Euler is best at 512 there
+int preferred_batch_width(int eq)
 {
     if (eq == SW_HEAT_F32)
         return 2048;
-    if (!is_euler(eq))
-        return 1024;
-    return is_flat(eq) ? 1024 : 512;
+    return (is_euler(eq) && !is_flat(eq)) ? 512 : 1024;
+}
+
+// workgroup size of a swept phase when the caller gives none: Euler tiles of
+// 1024 cells or more run 512 threads (twice the resident waves per compute
+// unit at the same LDS), everything else W rounded up to whole waves, at
+// most 256
+int default_threads(int eq, int w)
+{
+    if (is_euler(eq) && w >= 1024)
+        return 512;
+    return sw::default_phase_threads(w);
 }
 
 
@@ -106,9 +125,9 @@ bool width_ok(int eq, int64_t n, int64_t w)
     return w >= step && (w % step) == 0 && w <= max_width(eq) && (n % w) == 0 && n / w >= 2;
 }
 
-int default_width(int eq, int64_t n)
+int default_width(int eq, int64_t n, bool batch)
 {
-    for (int64_t w = preferred_width(eq); w >= 2; w -= 2)
+    for (int64_t w = batch ? preferred_batch_width(eq) : preferred_width(eq); w >= 2; w -= 2)
         if (width_ok(eq, n, w))
             return (int)w;
     return 0;
@@ -406,18 +425,19 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
                             o->width, (long long)n, max_width(eq));
             w = o->width;
         } else {
-            w = chosen_width(-1, eq, n, &tuned_threads);
+            w = chosen_width(-1, eq, n, &tuned_threads, false);
             if (!w)
                 return fail(SW_ERR_UNSUPPORTED, "no valid triangle width for n_cells %lld",
                             (long long)n);
         }
     }
-    if (o && o->threads && o->threads != 64 && o->threads != 128 && o->threads != 256)
-        return fail(SW_ERR_ARG, "threads must be 0, 64, 128 or 256");
+    if (o && o->threads && o->threads != 64 && o->threads != 128 && o->threads != 256 &&
+        o->threads != 512)
+        return fail(SW_ERR_ARG, "threads must be 0, 64, 128, 256 or 512");
     if (o && o->d_workspace && ((uintptr_t)o->d_workspace & 255) != 0)
         return fail(SW_ERR_ARG, "workspace must be 256-byte aligned");
     const int threads = (o && o->threads) ? o->threads
-                        : (tuned_threads ? tuned_threads : sw::default_phase_threads(w));
+                        : (tuned_threads ? tuned_threads : default_threads(eq, w));
     // a launch holds at most 2^32 - 1 work-items: one workgroup per tile in
     // a swept phase, at most one work-item per cell in a classic sub-step
     if (method == SW_METHOD_SWEPT
@@ -476,7 +496,15 @@ int sw_default_width(int eq, int64_t n_cells)
 {
     if (!valid_eq(eq) || n_cells < 4 || n_cells > kMaxCells)
         return 0;
-    return default_width(eq, n_cells);
+    return default_width(eq, n_cells, false);
+}
+
+int sw_default_threads(int eq, int width)
+{
+    if (!valid_eq(eq) || width < 2 * radius(eq) || width > max_width(eq) ||
+        width % (2 * radius(eq)) != 0)
+        return 0;
+    return default_threads(eq, width);
 }
 
 int swept_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx, void *d_state,

@@ -131,16 +131,18 @@ k_euler_f32_naive_flux(int t, float *__restrict__ q0c, float *__restrict__ q1,
     }
 }
 
-template <typename K64, typename K128, typename K256, typename... Args>
-hipError_t launch_by_threads(int nt, K64 k64, K128 k128, K256 k256, dim3 grid, size_t lds,
-                             hipStream_t s, Args... args)
+template <typename K64, typename K128, typename K256, typename K512, typename... Args>
+hipError_t launch_by_threads(int nt, K64 k64, K128 k128, K256 k256, K512 k512, dim3 grid,
+                             size_t lds, hipStream_t s, Args... args)
 {
     if (nt == 64)
         hipLaunchKernelGGL(k64, grid, dim3(64), lds, s, args...);
     else if (nt == 128)
         hipLaunchKernelGGL(k128, grid, dim3(128), lds, s, args...);
-    else
+    else if (nt == 256)
         hipLaunchKernelGGL(k256, grid, dim3(256), lds, s, args...);
+    else
+        hipLaunchKernelGGL(k512, grid, dim3(512), lds, s, args...);
     return hipGetLastError();
 }
 
@@ -151,6 +153,14 @@ hipError_t euler_f64_swept_phase(const PhaseLaunch &p, double *state, const doub
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellEulerF64;
     const dim3 g = dim3((unsigned)(p.n / p.w));
+    if (p.threads == 512) {
+        switch (p.w) {  // the default launch of Euler tiles of 1024 cells and more
+        case 1024: return launch_kernel(k_euler_f64_phase<512, 1024>, g, 512, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        default: break;
+        }
+    }
     if (p.threads == 256) {
         switch (p.w) {  // widths with compile-time LDS offsets
         case 128: return launch_kernel(k_euler_f64_phase<256, 128>, g, 256, lds, s,
@@ -168,7 +178,7 @@ hipError_t euler_f64_swept_phase(const PhaseLaunch &p, double *state, const doub
         default: break;
         }
     }
-    return launch_by_threads(p.threads, k_euler_f64_phase<64, 0>, k_euler_f64_phase<128, 0>, k_euler_f64_phase<256, 0>, g, lds, s,
+    return launch_by_threads(p.threads, k_euler_f64_phase<64, 0>, k_euler_f64_phase<128, 0>, k_euler_f64_phase<256, 0>, k_euler_f64_phase<512, 0>, g, lds, s,
         state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam, (int)p.first,
         (int)p.last);
 }
@@ -191,6 +201,14 @@ hipError_t euler_f32_swept_phase(const PhaseLaunch &p, float *state, const void 
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellEulerF32;
     const dim3 g = dim3((unsigned)(p.n / p.w));
+    if (p.threads == 512) {
+        switch (p.w) {  // the default launch of Euler tiles of 1024 cells and more
+        case 1024: return launch_kernel(k_euler_f32_phase<512, 1024>, g, 512, lds, s,
+            state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam,
+            (int)p.first, (int)p.last);
+        default: break;
+        }
+    }
     if (p.threads == 256) {
         switch (p.w) {  // widths with compile-time LDS offsets
         case 256: return launch_kernel(k_euler_f32_phase<256, 256>, g, 256, lds, s,
@@ -205,7 +223,7 @@ hipError_t euler_f32_swept_phase(const PhaseLaunch &p, float *state, const void 
         default: break;
         }
     }
-    return launch_by_threads(p.threads, k_euler_f32_phase<64, 0>, k_euler_f32_phase<128, 0>, k_euler_f32_phase<256, 0>, g, lds, s,
+    return launch_by_threads(p.threads, k_euler_f32_phase<64, 0>, k_euler_f32_phase<128, 0>, k_euler_f32_phase<256, 0>, k_euler_f32_phase<512, 0>, g, lds, s,
         state, ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, lam, (int)p.first,
         (int)p.last);
 }

@@ -100,16 +100,18 @@ k_heat_f32_naive4(const float *__restrict__ u, float *__restrict__ v, float *__r
     *(float4 *)(c + i0) = k;
 }
 
-template <typename K64, typename K128, typename K256, typename... Args>
-hipError_t launch_by_threads(int nt, K64 k64, K128 k128, K256 k256, dim3 grid, size_t lds,
-                             hipStream_t s, Args... args)
+template <typename K64, typename K128, typename K256, typename K512, typename... Args>
+hipError_t launch_by_threads(int nt, K64 k64, K128 k128, K256 k256, K512 k512, dim3 grid,
+                             size_t lds, hipStream_t s, Args... args)
 {
     if (nt == 64)
         hipLaunchKernelGGL(k64, grid, dim3(64), lds, s, args...);
     else if (nt == 128)
         hipLaunchKernelGGL(k128, grid, dim3(128), lds, s, args...);
-    else
+    else if (nt == 256)
         hipLaunchKernelGGL(k256, grid, dim3(256), lds, s, args...);
+    else
+        hipLaunchKernelGGL(k512, grid, dim3(512), lds, s, args...);
     return hipGetLastError();
 }
 
@@ -120,7 +122,7 @@ hipError_t heat_f64_swept_phase(const PhaseLaunch &p, double *state, const doubl
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellHeatF64;
     return launch_by_threads(p.threads, k_heat_f64_phase<64>, k_heat_f64_phase<128>,
-                             k_heat_f64_phase<256>, dim3((unsigned)(p.n / p.w)), lds, s, state,
+                             k_heat_f64_phase<256>, k_heat_f64_phase<512>, dim3((unsigned)(p.n / p.w)), lds, s, state,
                              ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, r,
                              (int)p.first, (int)p.last);
 }
@@ -144,7 +146,7 @@ hipError_t heat_f32_swept_phase(const PhaseLaunch &p, float *state, const float 
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellHeatF32;
     return launch_by_threads(p.threads, k_heat_f32_phase<64>, k_heat_f32_phase<128>,
-                             k_heat_f32_phase<256>, dim3((unsigned)(p.n / p.w)), lds, s, state,
+                             k_heat_f32_phase<256>, k_heat_f32_phase<512>, dim3((unsigned)(p.n / p.w)), lds, s, state,
                              ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, r,
                              (int)p.first, (int)p.last);
 }

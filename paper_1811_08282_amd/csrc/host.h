@@ -24,9 +24,12 @@ int radius(int eq);
 int lds_per_cell(int eq);
 int struct_bytes(int eq);
 int preferred_width(int eq);
+int preferred_batch_width(int eq);
+int default_threads(int eq, int w);
 int max_width(int eq);
 bool width_ok(int eq, int64_t n, int64_t w);
-int default_width(int eq, int64_t n);
+// largest valid width up to the preferred one (of the batch kernel if batch)
+int default_width(int eq, int64_t n, bool batch);
 size_t round_up(size_t x, size_t a);
 size_t swept_copy_bytes(int eq, int64_t n);
 int check_common(int eq, int64_t n, int64_t steps, double dt, double dx, const void *state,
@@ -35,8 +38,9 @@ int check_device_pointer(const void *p, int *dev_out);
 int launched(hipError_t e, const char *what);
 
 // width of a swept solve when the caller gives none: the tuned width of
-// (device, eq, n) if sw_autotune recorded one, else default_width
-int chosen_width(int dev, int eq, int64_t n, int *threads);
+// (device, eq, n) if sw_autotune recorded one, else default_width; threads
+// (if not NULL) receives the tuned workgroup size, else default_threads
+int chosen_width(int dev, int eq, int64_t n, int *threads, bool batch);
 
 } // namespace host
 } // namespace sw

@@ -36,10 +36,11 @@ struct PhaseLaunch {
     int j_first, j_last;
     bool first;       // reads the caller's state (level 0 of this call)
     bool last;        // writes the caller's state (final level)
-    int threads;      // workgroup size: 64, 128 or 256
+    int threads;      // workgroup size: 64, 128, 256 or 512
 };
 
-// Default workgroup size of a swept phase for tile width w.
+// Workgroup size of a swept phase for tile width w: whole waves covering the
+// tile, at most 256 (the host raises Euler tiles of 1024 cells and more to 512).
 inline int default_phase_threads(int w)
 {
     const int t = ((w + 63) / 64) * 64;

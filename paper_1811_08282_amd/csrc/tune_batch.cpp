@@ -106,7 +106,7 @@ void load_tune_file_locked()
     long long n;
     double ms;
     while (fscanf(f, "%63s %d %lld %d %d %lf", arch, &eq, &n, &w, &t, &ms) == 6) {
-        if (valid_eq(eq) && width_ok(eq, n, w) && (t == 64 || t == 128 || t == 256))
+        if (valid_eq(eq) && width_ok(eq, n, w) && (t == 64 || t == 128 || t == 256 || t == 512))
             record_tune_locked(std::string(arch), eq, (int64_t)n, TuneEntry{w, t, ms});
     }
     fclose(f);
@@ -125,7 +125,7 @@ void store_tune_file_locked(const std::string &arch, int eq, int64_t n, const Tu
     fclose(f);
 }
 
-int chosen_width(int dev, int eq, int64_t n, int *threads)
+int chosen_width(int dev, int eq, int64_t n, int *threads, bool batch)
 {
     {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
@@ -150,9 +150,9 @@ int chosen_width(int dev, int eq, int64_t n, int *threads)
             }
         }
     }
-    const int w = default_width(eq, n);
+    const int w = default_width(eq, n, batch);
     if (threads)
-        *threads = default_phase_threads(w);
+        *threads = default_threads(eq, w);
     return w;
 }
 
@@ -297,7 +297,7 @@ int sw_autotune(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream, 
     const double dt = 0.1, dx = 1.0;
     for (size_t ci = 0; ci < cands.size() && rc == SW_OK; ++ci) {
         const int w = cands[ci];
-        for (int threads = 256; threads >= 64 && rc == SW_OK; threads /= 2) {
+        for (int threads = 512; threads >= 64 && rc == SW_OK; threads /= 2) {
             if (threads > 64 && threads / 2 >= w)
                 continue;  // wider workgroups than the tile only idle
             sw_opts o{w, threads, ws, wbytes};
@@ -416,7 +416,7 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
         const sw_problem &p = problems[i];
         int w = p.width;
         if (!w) {
-            w = chosen_width(dev, p.eq, p.n_cells, nullptr);
+            w = chosen_width(dev, p.eq, p.n_cells, nullptr, true);
             if (!w)
                 return fail(SW_ERR_UNSUPPORTED, "problem %d: no valid width for n_cells %lld", i,
                             (long long)p.n_cells);
@@ -647,7 +647,7 @@ int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
     std::vector<int> widths(n_problems);
     for (int i = 0; i < n_problems; ++i) {
         widths[i] = problems[i].width ? problems[i].width
-                                      : chosen_width(dev, problems[i].eq, problems[i].n_cells, nullptr);
+                                      : chosen_width(dev, problems[i].eq, problems[i].n_cells, nullptr, true);
         if (!widths[i])
             return fail(SW_ERR_UNSUPPORTED, "problem %d: no valid width for n_cells %lld", i,
                         (long long)problems[i].n_cells);

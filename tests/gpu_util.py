@@ -29,12 +29,12 @@ def pack(eq, q):
     return np.concatenate([q.astype(np.float32), np.zeros(q.shape, np.float32)])
 
 
-def run(eq, host_state, steps, dt, dx, method="swept", width=0, chunks=None):
+def run(eq, host_state, steps, dt, dx, method="swept", width=0, chunks=None, threads=0):
     """Upload, solve (optionally as several calls), download."""
     import torch
     t = torch.from_numpy(np.ascontiguousarray(host_state)).cuda()
     for part in (chunks or [steps]):
-        sw.solve(eq, t, part, dt, dx, method=method, width=width)
+        sw.solve(eq, t, part, dt, dx, method=method, width=width, threads=threads)
     torch.cuda.synchronize()
     return t.cpu().numpy()
 

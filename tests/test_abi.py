@@ -56,15 +56,32 @@ def test_width_limits():
         assert wmax % (2 * rad) == 0 and (wmax + 2 * rad) * per_cell <= 160 * 1024
         assert wmax <= 8192
     assert sw.sw_default_width(sw.HEAT_F64, 1 << 22) == 1024
-    assert sw.sw_default_width(sw.EULER_F64, 1 << 22) == 512
+    assert sw.sw_default_width(sw.EULER_F64, 1 << 22) == 1024
+    assert sw.sw_default_width(sw.EULER_F32, 1 << 24) == 1024
     assert sw.sw_default_width(sw.HEAT_F32, 1 << 24) == 2048
     assert sw.sw_default_width(sw.HEAT_F64, 1000) == 500  # largest even divisor with n/W >= 2
     assert sw.sw_default_width(sw.HEAT_F64, 1001) == 0    # odd: no even divisor
     assert sw.sw_default_width(sw.HEAT_F64, 6) == 2
     # flattened Euler needs widths that are multiples of 4
     assert sw.sw_default_width(sw.EULER_F64_FLAT, 1 << 22) == 1024
+    assert sw.sw_default_width(sw.EULER_F32_FLAT, 1 << 24) == 2048
     assert sw.sw_default_width(sw.EULER_F64_FLAT, 24) == 12
     assert sw.sw_default_width(sw.EULER_F64_FLAT, 18) == 0
+
+
+def test_default_threads():
+    # Euler tiles of 1024 cells and more: 512 threads; else whole waves up to 256
+    for eq in (sw.EULER_F64, sw.EULER_F32, sw.EULER_F64_FLAT, sw.EULER_F32_FLAT):
+        assert sw.sw_default_threads(eq, 1024) == 512
+        assert sw.sw_default_threads(eq, 2048) == 512
+        assert sw.sw_default_threads(eq, 512) == 256
+        assert sw.sw_default_threads(eq, 100) == 128
+    assert sw.sw_default_threads(sw.HEAT_F64, 1024) == 256
+    assert sw.sw_default_threads(sw.HEAT_F32, 2048) == 256
+    assert sw.sw_default_threads(sw.HEAT_F64, 2) == 64
+    assert sw.sw_default_threads(sw.EULER_F64_FLAT, 34) == 0   # not a multiple of 4
+    assert sw.sw_default_threads(sw.HEAT_F64, 1 << 20) == 0    # wider than the LDS allows
+    assert sw.sw_default_threads(9, 64) == 0
 
 
 FAKE = 0x1000  # never dereferenced: every case below fails or returns before any HIP call
@@ -118,6 +135,7 @@ def test_misaligned_workspace_rejected():
 def test_python_binding_names_match_c_abi():
     for name in ("swept_solve", "naive_solve", "swept_solve_ex", "naive_solve_ex",
                  "sw_state_bytes", "sw_workspace_bytes", "sw_max_width", "sw_default_width",
+                 "sw_default_threads",
                  "sw_phase_count", "sw_phase_info", "sw_phase_interval", "sw_release"):
         assert callable(getattr(sw, name))
     assert ctypes.sizeof(sw.sw_opts) == 24
@@ -136,3 +154,13 @@ def test_launch_work_item_limit_rejected_on_host():
     assert sw.naive_solve(sw.EULER_F64, (1 << 32) - 256, 0, 0.1, 1.0, FAKE, None) == sw.SW_OK
     assert sw.swept_solve_ex(sw.HEAT_F64, big, 0, 0.25, 1.0, FAKE, None, width=2048,
                              threads=256) == sw.SW_OK
+
+
+def test_workgroup_sizes_checked_on_host():
+    for threads in (32, 96, 1024):
+        rc = sw.swept_solve_ex(sw.EULER_F64, 4096, 5, 0.1, 1.0, FAKE, None, width=1024,
+                               threads=threads)
+        assert rc == sw.SW_ERR_ARG and "threads" in sw.last_error()
+    for threads in (64, 128, 256, 512):  # accepted (zero steps: no device call)
+        assert sw.swept_solve_ex(sw.EULER_F64, 4096, 0, 0.1, 1.0, FAKE, None, width=1024,
+                                 threads=threads) == sw.SW_OK

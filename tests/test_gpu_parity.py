@@ -262,3 +262,36 @@ def test_widest_tile_of_every_equation(eq):
     else:
         want = np.concatenate(oracle.euler_f32(host[:3], host[3:], steps, dt / dx))
     assert np.array_equal(swept, want)
+
+
+@pytest.mark.parametrize("eq", [sw.HEAT_F64, sw.HEAT_F32, sw.EULER_F64, sw.EULER_F32,
+                                sw.EULER_F64_FLAT, sw.EULER_F32_FLAT])
+def test_512_thread_workgroups_every_equation(eq):
+    """Eight-wave workgroups (the default launch of Euler tiles of 1024 cells
+    and more) at compile-time widths (1024, 2048) and a run-time one (1536):
+    bit-identical to the oracle of the same precision for step counts that
+    end inside the first, second and later phases."""
+    n = 3 * 2048
+    if eq in (sw.HEAT_F64, sw.HEAT_F32):
+        q0 = heat_ic(n, 31)
+        dt, dx = 0.25, 1.0
+    else:
+        q0 = sod_tiled(n, 1024)
+        q0[1] += 0.05 * q0[0]
+        dt, dx = 0.1, 1.0
+    layout = {sw.EULER_F64_FLAT: sw.EULER_F64, sw.EULER_F32_FLAT: sw.EULER_F32}.get(eq, eq)
+    host = pack(layout, q0)
+    for w in (1024, 1536, 2048):
+        half_steps = (w // (2 * sw.radius(eq))) // sw.substeps(eq)
+        for steps in (1, half_steps, half_steps + 1, 3 * half_steps + 7):
+            announce("512 threads eq", eq, "W", w, "steps", steps)
+            got = run(eq, host, steps, dt, dx, "swept", width=w, threads=512)
+            if eq == sw.HEAT_F64:
+                want = oracle.heat_f64(host[0], steps, dt / dx ** 2).reshape(1, -1)
+            elif eq == sw.HEAT_F32:
+                want = np.stack(oracle.heat_f32(host[0], host[1], steps, dt / dx ** 2))
+            elif eq in (sw.EULER_F64, sw.EULER_F64_FLAT):
+                want = oracle.euler_f64(host, steps, dt / dx)
+            else:
+                want = np.concatenate(oracle.euler_f32(host[:3], host[3:], steps, dt / dx))
+            assert np.array_equal(got, want), (eq, w, steps)
