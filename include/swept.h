@@ -43,8 +43,12 @@
  * alone is a complete checkpoint: solving n1 then n2 steps equals n1 + n2.
  *
  * Ownership: the caller owns d_state; the library never frees caller memory.
- * Working arrays are owned and cached by the library (released by
- * sw_release()) unless the caller passes one in sw_opts.
+ * Working arrays are owned and cached by the library, one set per (device,
+ * stream), unless the caller passes one in sw_opts.  A call that needs more
+ * than the cached set holds synchronises the device, frees it and allocates
+ * a larger one; sw_release() frees every set.  Calls on one stream from
+ * several host threads at once must therefore not grow that stream's set or
+ * race sw_release(): size it with a first call, or pass workspaces.
  *
  * Asynchrony: calls enqueue on `stream` (a hipStream_t; NULL = null stream)
  * and return without waiting.  A kernel fault surfaces at the caller's next
