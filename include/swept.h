@@ -226,7 +226,8 @@ void sw_tune_clear(void);
  * swept_solve of that problem with the same width.  Every wait is bounded in
  * time: a wait that exceeds the bound aborts the whole launch, which then
  * reports SW_ERR_HIP from sw_batch_wait.  The persistent kernel runs
- * 256-thread workgroups; a problem without a width and without a tuned one
+ * 256-thread workgroups unless sw_batch_opts asks for 512 (the batch
+ * autotuner tries both); a problem without a width and without a tuned one
  * takes the largest valid width up to 1024 (heat binary32 2048, lengthened
  * Euler 512), and the LDS of the widest tile sets the resident workgroups
  * per CU of the whole batch. */
@@ -242,7 +243,7 @@ typedef struct {
 
 typedef struct {
     int blocks_per_cu;     /* resident workgroups per CU, 0 = occupancy limit */
-    int reserved0;
+    int threads;           /* workgroup size: 256 or 512, 0 = 256              */
     int64_t wait_limit_us; /* bound of one dependency wait, 0 = 10 s           */
 } sw_batch_opts;
 
@@ -280,14 +281,18 @@ int swept_solve_batch(int n_problems, const sw_problem *problems, sw_stream stre
  * the same steps per problem: min(n_steps, probe_steps), or with
  * probe_steps = 0 enough steps for four phases at the widest power-of-two
  * width of the problem's equation.
+ * For each workgroup size, 256 and 512 threads (only best->threads if it
+ * is nonzero on input):
  *  1. widths, one equation at a time: every problem of that equation given
  *     with width 0 takes the largest valid width not above a cap, for caps
- *     64, 128, ... up to the widest tile; the fastest cap is kept;
+ *     64, 128, ... up to the widest tile (512, 1024, ... for 512 threads,
+ *     starting from the widths chosen for 256); the fastest cap is kept;
  *  2. resident workgroups per CU: 1, 2, ... up to the occupancy limit.
- * On success the chosen widths are written into problems[i].width for every
- * problem given with width 0, best->blocks_per_cu is set (0 = occupancy
- * limit was fastest; wait_limit_us = 0) and *best_ms_per_update (may be
- * NULL) gets the fastest probe's time per cell-update.  Synchronous; not
+ * The fastest combination wins.  On success its widths are written into
+ * problems[i].width for every problem given with width 0, best->threads and
+ * best->blocks_per_cu are set (0 = the occupancy limit was fastest;
+ * wait_limit_us = 0) and *best_ms_per_update (may be NULL) gets the fastest
+ * probe's time per cell-update.  Synchronous; not
  * allowed during stream capture (SW_ERR_CAPTURE); needs device memory for
  * one copy of every state plus one batch's working arrays (SW_ERR_NOMEM
  * otherwise).  Other errors as sw_batch_create. */

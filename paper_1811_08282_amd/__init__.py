@@ -49,7 +49,7 @@ class sw_problem(ctypes.Structure):
 
 
 class sw_batch_opts(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", ctypes.c_int), ("reserved0", ctypes.c_int),
+    _fields_ = [("blocks_per_cu", ctypes.c_int), ("threads", ctypes.c_int),
                 ("wait_limit_us", ctypes.c_int64)]
 
 
@@ -261,9 +261,9 @@ def sw_batch_item_deps(phase, tile, tiles, single_phase=0):
 class Batch:
     """Owner of an sw_batch handle (see include/swept.h)."""
 
-    def __init__(self, problems, blocks_per_cu=0, wait_limit_us=0):
+    def __init__(self, problems, blocks_per_cu=0, wait_limit_us=0, threads=0):
         self._arr = problem_array(problems)
-        opts = sw_batch_opts(int(blocks_per_cu), 0, int(wait_limit_us))
+        opts = sw_batch_opts(int(blocks_per_cu), int(threads), int(wait_limit_us))
         h = ctypes.c_void_p()
         rc = load().sw_batch_create(len(self._arr), self._arr, ctypes.byref(opts), ctypes.byref(h))
         if rc:
@@ -299,13 +299,15 @@ class Batch:
             pass
 
 
-def sw_batch_autotune(problems, probe_steps=0, stream=None):
+def sw_batch_autotune(problems, probe_steps=0, stream=None, threads=0):
     """Tune the batched launch (see include/swept.h): the problems' states are
     only read; every problem given with width 0 gets the chosen width written
-    back into its dict.  Returns (blocks_per_cu, ms per cell-update of the
-    fastest probe); raises on failure."""
+    back into its dict.  ``threads`` = 0 tries 256- and 512-thread workgroups,
+    else only that size.  Returns (blocks_per_cu, threads, ms per cell-update
+    of the fastest probe); raises on failure."""
     arr = problem_array(problems)
     best = sw_batch_opts()
+    best.threads = int(threads)
     ms = ctypes.c_double()
     rc = load().sw_batch_autotune(len(arr), arr, int(probe_steps), stream, ctypes.byref(best),
                                   ctypes.byref(ms))
@@ -314,7 +316,7 @@ def sw_batch_autotune(problems, probe_steps=0, stream=None):
     for p, a in zip(problems, arr):
         if isinstance(p, dict) and not p.get("width"):
             p["width"] = a.width
-    return best.blocks_per_cu, ms.value
+    return best.blocks_per_cu, best.threads, ms.value
 
 
 def swept_solve_batch(problems, stream=None) -> int:

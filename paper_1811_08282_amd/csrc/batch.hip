@@ -1,6 +1,6 @@
 // batch.hip -- persistent kernel of the batched swept launch (tables and
-// ordering described in batch.h).  One workgroup of 256 threads runs one
-// work item at a time with the same tile-phase bodies as the per-phase
+// ordering described in batch.h).  One workgroup (256 or 512 threads) runs
+// one work item at a time with the same tile-phase bodies as the per-phase
 // kernels, so a problem solved in a batch is bit-identical to the same
 // problem solved alone with the same width.
 //
@@ -15,8 +15,6 @@
 
 namespace sw {
 namespace {
-
-constexpr int kBatchThreads = 256;
 
 __device__ __forceinline__ int load_acquire(const int *p)
 {
@@ -62,7 +60,8 @@ __device__ void copy_out(const BatchProblem &P, int tile)
     }
 }
 
-__global__ void __launch_bounds__(kBatchThreads) k_batch_persistent(BatchTables b)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_batch_persistent(BatchTables b)
 {
     extern __shared__ double lds[];
     __shared__ long long s_item;
@@ -106,7 +105,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_persistent(BatchTables 
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
         if (P.single_phase && k == 2) {
-            copy_out<kBatchThreads>(P, t);
+            copy_out<NT>(P, t);
         } else {
             const int64_t half = P.w / (2 * P.radius);
             const PhaseRange pr = phase_range(k, P.final_level, half, P.radius);
@@ -124,27 +123,31 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_persistent(BatchTables 
             jb.first = (k == 1);
             jb.last = (k == P.phases) && !P.single_phase;
             jb.final_level = P.final_level;
+            // compile-time LDS offsets for the common Euler widths: 256 and
+            // 512 in four-wave workgroups, 512 and 1024 in eight-wave ones
+            constexpr int kWideA = NT >= 512 ? 1024 : 512;
+            constexpr int kWideB = NT >= 512 ? 512 : 256;
             switch (P.eq) {
-            case 0: heat_f64_tile<kBatchThreads>(jb, lds); break;
-            case 1: heat_f32_tile<kBatchThreads>(jb, (float *)lds); break;
-            case 2:  // compile-time LDS offsets for the common Euler widths
-                if (P.w == 512)
-                    euler_f64_tile<kBatchThreads, 512>(jb, lds);
-                else if (P.w == 256)
-                    euler_f64_tile<kBatchThreads, 256>(jb, lds);
+            case 0: heat_f64_tile<NT>(jb, lds); break;
+            case 1: heat_f32_tile<NT>(jb, (float *)lds); break;
+            case 2:
+                if (P.w == kWideA)
+                    euler_f64_tile<NT, kWideA>(jb, lds);
+                else if (P.w == kWideB)
+                    euler_f64_tile<NT, kWideB>(jb, lds);
                 else
-                    euler_f64_tile<kBatchThreads>(jb, lds);
+                    euler_f64_tile<NT>(jb, lds);
                 break;
             case 3:
-                if (P.w == 512)
-                    euler_f32_tile<kBatchThreads, 512>(jb, lds);
-                else if (P.w == 256)
-                    euler_f32_tile<kBatchThreads, 256>(jb, lds);
+                if (P.w == kWideA)
+                    euler_f32_tile<NT, kWideA>(jb, lds);
+                else if (P.w == kWideB)
+                    euler_f32_tile<NT, kWideB>(jb, lds);
                 else
-                    euler_f32_tile<kBatchThreads>(jb, lds);
+                    euler_f32_tile<NT>(jb, lds);
                 break;
-            case 4: flat_f64_tile<kBatchThreads>(jb, lds); break;
-            default: flat_f32_tile<kBatchThreads>(jb, lds); break;
+            case 4: flat_f64_tile<NT>(jb, lds); break;
+            default: flat_f32_tile<NT>(jb, lds); break;
             }
         }
         // publish: every thread's stores reach device scope before the flag
@@ -190,16 +193,17 @@ hipError_t fill(T *p, int64_t count, T v, hipStream_t s)
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s) { return fill(p, count, v, s); }
 hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s) { return fill(p, count, v, s); }
 
-int batch_threads() { return kBatchThreads; }
-
-hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu)
+hipError_t batch_occupancy(size_t lds_bytes, int threads, int *blocks_per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent,
-                                                        kBatchThreads, lds_bytes);
+    if (threads == 512)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            blocks_per_cu, k_batch_persistent<512>, 512, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent<256>,
+                                                        256, lds_bytes);
 }
 
-hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, size_t lds_bytes,
-                        hipStream_t s)
+hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, int threads,
+                        size_t lds_bytes, hipStream_t s)
 {
     const int64_t rb = (n_flags + 255) / 256;
     const unsigned reset_blocks = (unsigned)(rb < 1 ? 1 : (rb > 4096 ? 4096 : rb));
@@ -208,8 +212,12 @@ hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, size_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_batch_persistent, dim3((unsigned)blocks), dim3(kBatchThreads), lds_bytes,
-                       s, t);
+    if (threads == 512)
+        hipLaunchKernelGGL(k_batch_persistent<512>, dim3((unsigned)blocks), dim3(512), lds_bytes,
+                           s, t);
+    else
+        hipLaunchKernelGGL(k_batch_persistent<256>, dim3((unsigned)blocks), dim3(256), lds_bytes,
+                           s, t);
     return hipGetLastError();
 }
 

@@ -34,10 +34,9 @@
 
 namespace sw {
 
-int batch_threads();
-hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu);
-hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, size_t lds_bytes,
-                        hipStream_t s);
+hipError_t batch_occupancy(size_t lds_bytes, int threads, int *blocks_per_cu);
+hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, int threads,
+                        size_t lds_bytes, hipStream_t s);
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s);
 hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s);
 
@@ -221,6 +220,7 @@ struct sw_batch_impl {
     int64_t items = 0;
     int64_t flags = 0;
     int blocks = 0;
+    int threads = 256;
     std::vector<int> widths;
 };
 
@@ -387,6 +387,9 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
         return fail(SW_ERR_ARG, "empty problem list");
     if (opts && (opts->blocks_per_cu < 0 || opts->wait_limit_us < 0))
         return fail(SW_ERR_ARG, "invalid batch options");
+    if (opts && opts->threads != 0 && opts->threads != 256 && opts->threads != 512)
+        return fail(SW_ERR_ARG, "batch threads must be 0, 256 or 512");
+    const int threads = (opts && opts->threads) ? opts->threads : 256;
     for (int i = 0; i < n_problems; ++i) {
         const sw_problem &p = problems[i];
         int rc = check_common(p.eq, p.n_cells, p.n_steps, p.dt, p.dx, p.d_state, 4);
@@ -458,6 +461,7 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
 
     sw_batch_impl *b = new sw_batch_impl();
     b->device = dev;
+    b->threads = threads;
     b->widths = widths;
     b->items = items;
     b->flags = flags;
@@ -503,7 +507,7 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
 
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        sw::batch_occupancy(max_lds, &per_cu) != hipSuccess || per_cu < 1) {
+        sw::batch_occupancy(max_lds, threads, &per_cu) != hipSuccess || per_cu < 1) {
         (void)hipGetLastError();
         free_batch(b);
         return fail(SW_ERR_HIP, "batch occupancy query failed (LDS %zu bytes)", max_lds);
@@ -521,7 +525,7 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
     if (e == hipSuccess)
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = sw::batch_launch(t, flags, b->blocks, max_lds, cap);
+        hipError_t le = sw::batch_launch(t, flags, b->blocks, threads, max_lds, cap);
         e = hipStreamEndCapture(cap, &b->graph);
         if (le != hipSuccess)
             e = le;
@@ -623,6 +627,9 @@ int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
         return fail(SW_ERR_ARG, "empty problem list");
     if (probe_steps < 0 || probe_steps > 1000000)
         return fail(SW_ERR_ARG, "probe_steps out of range");
+    const int only_threads = best->threads;  // 0: try both workgroup sizes
+    if (only_threads != 0 && only_threads != 256 && only_threads != 512)
+        return fail(SW_ERR_ARG, "best->threads must be 0, 256 or 512");
     for (int i = 0; i < n_problems; ++i) {
         const sw_problem &p = problems[i];
         int rc = check_common(p.eq, p.n_cells, p.n_steps, p.dt, p.dx, p.d_state, 4);
@@ -696,17 +703,18 @@ int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
         work += (double)problems[i].n_cells * (double)steps[i];
     }
 
-    // one probe: the batch with widths `ws` and `bpc` workgroups per CU; the
-    // result is the ms of the timed run (after one warm-up run)
+    // one probe: the batch with widths `ws`, `bpc` workgroups per CU of
+    // `threads` threads; the result is the ms of the timed run (after one
+    // warm-up run)
     int max_bpc = 0;
-    auto probe = [&](const std::vector<int> &ws, int bpc, double *ms_out) -> int {
+    auto probe = [&](const std::vector<int> &ws, int bpc, int threads, double *ms_out) -> int {
         std::vector<sw_problem> sp(problems, problems + n_problems);
         for (int i = 0; i < n_problems; ++i) {
             sp[i].d_state = buf + offs[i];
             sp[i].width = ws[i];
             sp[i].n_steps = steps[i];
         }
-        sw_batch_opts o{bpc, 0, 0};
+        sw_batch_opts o{bpc, threads, 0};
         sw_batch b = nullptr;
         int r = sw_batch_create(n_problems, sp.data(), &o, &b);
         if (r)
@@ -739,50 +747,68 @@ int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
         return SW_OK;
     };
 
+    // For each workgroup size (four and eight waves):
     // 1. widths, one equation at a time: every problem of that equation that
     //    leaves its width to the library takes the largest valid width up to
-    //    a cap; caps 64, 128, ... up to the equation's widest tile
-    double top = INFINITY;
-    if (rc == SW_OK)
-        rc = probe(widths, 0, &top);
+    //    a cap; caps 64, 128, ... up to the equation's widest tile (eight-wave
+    //    workgroups start from the four-wave choice and try caps from 512 up:
+    //    narrower tiles leave most of their waves idle);
+    // 2. resident workgroups per CU for those widths (0 = occupancy limit).
+    // The fastest (widths, workgroup size, workgroups per CU) wins.
     std::vector<int> eqs;
     for (int i = 0; i < n_problems; ++i)
         if (!problems[i].width && std::find(eqs.begin(), eqs.end(), problems[i].eq) == eqs.end())
             eqs.push_back(problems[i].eq);
-    for (size_t k = 0; k < eqs.size() && rc == SW_OK; ++k) {
-        const int e = eqs[k];
-        const int step = 2 * radius(e);
-        for (int cap = 64; cap <= max_width(e) && rc == SW_OK; cap *= 2) {
-            std::vector<int> cand = widths;
-            for (int i = 0; i < n_problems; ++i) {
-                if (problems[i].width || problems[i].eq != e)
+    const std::vector<int> start = widths;
+    double best_ms = INFINITY;
+    int best_bpc = 0, best_threads = 256;
+    for (int threads = 256; threads <= 512 && rc == SW_OK; threads *= 2) {
+        if (only_threads && threads != only_threads)
+            continue;
+        std::vector<int> ws = best_ms < INFINITY ? widths : start;
+        double top = INFINITY;
+        rc = probe(ws, 0, threads, &top);
+        for (size_t k = 0; k < eqs.size() && rc == SW_OK; ++k) {
+            const int e = eqs[k];
+            const int step = 2 * radius(e);
+            for (int cap = threads >= 512 ? 512 : 64; cap <= max_width(e) && rc == SW_OK;
+                 cap *= 2) {
+                std::vector<int> cand = ws;
+                for (int i = 0; i < n_problems; ++i) {
+                    if (problems[i].width || problems[i].eq != e)
+                        continue;
+                    for (int w = cap - cap % step; w >= step; w -= step)
+                        if (width_ok(e, problems[i].n_cells, w)) {
+                            cand[i] = w;
+                            break;
+                        }
+                }
+                if (cand == ws)
                     continue;
-                for (int w = cap - cap % step; w >= step; w -= step)
-                    if (width_ok(e, problems[i].n_cells, w)) {
-                        cand[i] = w;
-                        break;
-                    }
-            }
-            if (cand == widths)
-                continue;
-            double t = 0.0;
-            rc = probe(cand, 0, &t);
-            if (rc == SW_OK && t < top) {
-                top = t;
-                widths = cand;
+                double t = 0.0;
+                rc = probe(cand, 0, threads, &t);
+                if (rc == SW_OK && t < top) {
+                    top = t;
+                    ws = cand;
+                }
             }
         }
-    }
-    // 2. resident workgroups per CU for those widths (0 = occupancy limit)
-    int top_bpc = 0;
-    if (rc == SW_OK)
-        rc = probe(widths, 0, &top);  // also sets max_bpc for these widths
-    for (int bpc = 1; bpc < max_bpc && rc == SW_OK; ++bpc) {
-        double t = 0.0;
-        rc = probe(widths, bpc, &t);
-        if (rc == SW_OK && t < top) {
-            top = t;
-            top_bpc = bpc;
+        int top_bpc = 0;
+        if (rc == SW_OK)
+            rc = probe(ws, 0, threads, &top);  // also sets max_bpc for these widths
+        for (int bpc = 1; bpc < max_bpc && rc == SW_OK; ++bpc) {
+            double t = 0.0;
+            rc = probe(ws, bpc, threads, &t);
+            if (rc == SW_OK && t < top) {
+                top = t;
+                top_bpc = bpc;
+            }
+        }
+        if (rc == SW_OK && top < best_ms) {
+            best_ms = top;
+            best_bpc = top_bpc;
+            best_threads = threads;
+            widths = ws;
         }
     }
     if (e0)
@@ -797,11 +823,11 @@ int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
     for (int i = 0; i < n_problems; ++i)
         if (!problems[i].width)
             problems[i].width = widths[i];
-    best->blocks_per_cu = top_bpc;
-    best->reserved0 = 0;
+    best->blocks_per_cu = best_bpc;
+    best->threads = best_threads;
     best->wait_limit_us = 0;
     if (best_ms_per_update)
-        *best_ms_per_update = work > 0.0 ? top / work : 0.0;
+        *best_ms_per_update = work > 0.0 ? best_ms / work : 0.0;
     return ok();
 }
 

@@ -64,14 +64,17 @@ MIXED = [
     (sw.HEAT_F32, 8192, 333, 1024, 8),
     (sw.EULER_F64_FLAT, 2048, 41, 128, 9),   # flattened layout, radius-2 halos
     (sw.EULER_F32_FLAT, 1024, 17, 4, 10),
+    (sw.EULER_F64, 3072, 300, 1024, 11),     # compile-time widths of both workgroup sizes
+    (sw.EULER_F32, 2048, 200, 512, 12),
 ]
 
 
-def test_mixed_batch_equals_individual_swept_and_oracle():
+@pytest.mark.parametrize("threads", [0, 512])
+def test_mixed_batch_equals_individual_swept_and_oracle(threads):
     import torch
     tensors, hosts, probs = _problems(MIXED)
-    announce("batch mixed", len(probs))
-    b = sw.Batch(probs)
+    announce("batch mixed", len(probs), "threads", threads)
+    b = sw.Batch(probs, threads=threads)
     items, blocks, nbytes = b.info()
     assert items > 0 and blocks > 0
     b.run(torch.cuda.current_stream().cuda_stream)
@@ -158,6 +161,8 @@ def test_batch_rejects_bad_problems():
     with pytest.raises(sw.SweptError):
         sw.Batch(bad)
     bad[0]["width"] = 64
+    with pytest.raises(sw.SweptError):
+        sw.Batch(bad, threads=128)  # the batch kernel has 256- and 512-thread forms only
     bad[0]["dt"] = -1.0
     with pytest.raises(sw.SweptError):
         sw.Batch(bad)
@@ -222,8 +227,8 @@ def test_batch_autotune_picks_widths_and_workgroups_reading_states_only():
              (sw.EULER_F64_FLAT, 256 * 8, 9, 0, 55)]
     tensors, hosts, probs = _problems(specs)
     announce("batch autotune")
-    bpc, ms = sw.sw_batch_autotune(probs, 8)
-    assert bpc >= 0 and ms > 0
+    bpc, threads, ms = sw.sw_batch_autotune(probs, 8)
+    assert bpc >= 0 and threads in (256, 512) and ms > 0
     for t, h in zip(tensors, hosts):
         assert np.array_equal(t.cpu().numpy(), h)  # read only
     assert probs[3]["width"] == 64  # a width given by the caller is kept
@@ -231,7 +236,7 @@ def test_batch_autotune_picks_widths_and_workgroups_reading_states_only():
         w = p["width"]
         step = 2 * sw.radius(p["eq"])
         assert w > 0 and w % step == 0 and p["n_cells"] % w == 0 and p["n_cells"] // w >= 2
-    b = sw.Batch(probs, blocks_per_cu=bpc)
+    b = sw.Batch(probs, blocks_per_cu=bpc, threads=threads)
     stream = torch.cuda.current_stream().cuda_stream
     b.run(stream)
     assert b.wait(stream) == sw.SW_OK, sw.last_error()

@@ -156,10 +156,19 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
         specs.append(dict(eq=eq, width=0, n_cells=p.n, n_steps=5000, dt=dt, dx=dx,
                           d_state=t.data_ptr()))
     torch.cuda.synchronize()
-    announce("fullsize batch autotune", eq_heat, eq_euler, "problems", len(specs))
-    bpc, probe_ms = sw.sw_batch_autotune(specs, 300)
-    announce("fullsize batch", eq_heat, eq_euler, "problems", len(specs), "blocks/CU", bpc)
-    b = sw.Batch(specs, blocks_per_cu=bpc)
+    # the tuner once per workgroup size, so that each step reports when done
+    tuned = []
+    for size in (256, 512):
+        cand = [dict(s) for s in specs]
+        announce("fullsize batch autotune", eq_heat, eq_euler, "problems", len(specs),
+                 "threads", size)
+        bpc, threads, per_update = sw.sw_batch_autotune(cand, 200, threads=size)
+        announce("tuned: blocks/CU", bpc, "threads", threads, "ms per cell-update", per_update)
+        tuned.append((per_update, bpc, threads, cand))
+    _, bpc, threads, specs = min(tuned, key=lambda x: x[0])
+    announce("fullsize batch", eq_heat, eq_euler, "problems", len(specs), "blocks/CU", bpc,
+             "threads", threads)
+    b = sw.Batch(specs, blocks_per_cu=bpc, threads=threads)
     stream = torch.cuda.current_stream().cuda_stream
     b.run(stream)
     assert b.wait(stream) == sw.SW_OK, sw.last_error()
@@ -191,6 +200,6 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
     ms = start.elapsed_time(stop)
     cells = sum(p.n for p in probs)
     record(f"batch_4096x5000_{'f64' if sw.is_f64(eq_heat) else 'f32'}", ms=ms, cells=cells,
-           cell_updates_per_s=cells * 5000 / (ms * 1e-3), blocks_per_cu=bpc,
+           cell_updates_per_s=cells * 5000 / (ms * 1e-3), blocks_per_cu=bpc, threads=threads,
            distinct_widths=len(set(widths)), widest=max(widths), narrowest=min(widths))
     b.close()
