@@ -113,7 +113,23 @@ __device__ __forceinline__ void heat_f32_tile(const TileJob &jb, float *ldsf)
         const int64_t m = jb.base + j;
         const float *src = (m & 1) ? s0 : s1;
         float *dst = (m & 1) ? s1 : s0;
-        for (int i = a + 1 + tid; i <= w - a; i += NT) {
+        // two cells per thread and pass (i and i + NT): the compiler pairs
+        // their LDS accesses (three instructions per cell instead of five)
+        // and shares the address arithmetic.  Measured 6 % faster at
+        // W = 2048; the binary64 loop above is bound by LDS bandwidth, and
+        // the same pairing there measured 13 % slower.
+        const int end = w - a;
+        int i = a + 1 + tid;
+        for (; i + NT <= end; i += 2 * NT) {
+            float c0 = cc[i], c1 = cc[i + NT];
+            const float x0 = heat_update_kahan(src[i - 1], src[i], src[i + 1], r, c0);
+            const float x1 = heat_update_kahan(src[i + NT - 1], src[i + NT], src[i + NT + 1], r, c1);
+            dst[i] = x0;
+            dst[i + NT] = x1;
+            cc[i] = c0;
+            cc[i + NT] = c1;
+        }
+        if (i <= end) {
             float comp = cc[i];
             dst[i] = heat_update_kahan(src[i - 1], src[i], src[i + 1], r, comp);
             cc[i] = comp;
