@@ -162,7 +162,7 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
         cand = [dict(s) for s in specs]
         announce("fullsize batch autotune", eq_heat, eq_euler, "problems", len(specs),
                  "threads", size)
-        bpc, threads, per_update = sw.sw_batch_autotune(cand, 200, threads=size)
+        bpc, threads, per_update = sw.sw_batch_autotune(cand, 100, threads=size)
         announce("tuned: blocks/CU", bpc, "threads", threads, "ms per cell-update", per_update)
         tuned.append((per_update, bpc, threads, cand))
     _, bpc, threads, specs = min(tuned, key=lambda x: x[0])
