@@ -135,6 +135,61 @@ def test_euler_f32_n16777216_20000_steps_error_vs_f64():
     assert rel1[0] < 1e-2 and rel1[2] < 1e-2
 
 
+def test_heat_f64_beyond_2_31_cells():
+    """A grid of 2^31 + 2^29 cells (cell offsets past the 32-bit range; 21 GB
+    of state, 86 GB of swept working arrays): swept and classic against the
+    oracle on dependency cones at the start, across 2^31 and at the periodic
+    seam.  The initial state is dyadic and generated on the device by integer
+    arithmetic that the host repeats exactly for the sampled windows."""
+    import torch
+    n, steps, r = (1 << 31) + (1 << 29), 600, 0.25
+
+    def ic_host(idx):
+        return ((idx.astype(np.int64) * 40503) % 1021).astype(np.float64) / 1024.0
+
+    def ic_device():
+        j = torch.arange(n, dtype=torch.int64, device="cuda")
+        j.mul_(40503).remainder_(1021)
+        u = j.to(torch.float64).div_(1024.0)
+        del j
+        return u.reshape(1, n)
+
+    span = 16
+    starts = [0, (1 << 31) - 8, n - 8]
+    want = {}
+    for s0 in starts:
+        idx = np.arange(s0 - steps - 1, s0 + span + steps + 1) % n
+        want[s0] = oracle.heat_f64(ic_host(idx), steps, r)[steps + 1: steps + 1 + span]
+    for method in ("swept", "naive"):
+        announce("beyond 2^31 cells heat_f64", method, n, steps)
+        u = ic_device()
+        sw.solve(sw.HEAT_F64, u, steps, r, 1.0, method=method)
+        torch.cuda.synchronize()
+        for s0 in starts:
+            sel = torch.arange(s0, s0 + span, device="cuda") % n
+            got = u[0, sel].cpu().numpy()
+            assert np.array_equal(got, want[s0]), (method, s0)
+        del u
+        sw.sw_release()
+        torch.cuda.empty_cache()
+
+
+def test_euler_f32_flat_n16777216_20000_steps():
+    """The flattened binary32 layout at full size (the launch bench.py times:
+    W = 2048, 512-thread workgroups) equals the binary32 oracle tile bit for
+    bit, and so the lengthened binary32 result."""
+    w = wl.EULER_PREC
+    q0 = wl.initial_state(w)
+    assert sw.sw_default_width(sw.EULER_F32_FLAT, w.n) == 2048
+    announce("fullsize euler_f32_flat swept", w.n, w.steps)
+    swept = run(sw.EULER_F32_FLAT, pack(sw.EULER_F32, q0), w.steps, w.dt, w.dx, "swept")
+    q32 = q0[:, :w.tile].astype(np.float32)
+    tq, tc = oracle.euler_f32(q32, np.zeros_like(q32), w.steps, w.dt / w.dx)
+    tiles = swept.reshape(6, w.n // w.tile, w.tile)
+    want = np.concatenate([tq, tc])
+    assert np.array_equal(tiles, np.broadcast_to(want[:, None, :], tiles.shape))
+
+
 @pytest.mark.parametrize("eq_heat,eq_euler", [(sw.HEAT_F64, sw.EULER_F64),
                                               (sw.HEAT_F32, sw.EULER_F32)])
 def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
