@@ -281,8 +281,17 @@ def cpu_baseline(work, eq, budget_s, gpu_final=None):
         "kind": "oracle",
         "sample": f"{cells} cells x {done} time steps of the same workload, "
                   f"{'binary64' if sw.is_f64(eq) else 'binary32 + Kahan'}, "
-                  f"{t_used:.1f} s wall on {oracle.threads_used()} OpenMP threads ({cpu_model()})",
+                  f"{t_used:.3g} s wall on {oracle.threads_used()} OpenMP threads ({cpu_model()})",
     }
+    if work.name == wl.HEAT_SMALL.name and eq == sw.HEAT_F64:
+        # the small configuration also on one host thread, whole workload
+        t0 = time.perf_counter()
+        oracle.heat_f64(wl.initial_state(work), work.steps, arg, threads=1)
+        t1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": work.n * work.steps / t1, "unit": "cell-updates/s",
+                                "cores": 1,
+                                "sample": f"the whole workload, {work.n} cells x {work.steps} "
+                                          f"time steps, {t1 * 1e3:.1f} ms"}
     if gpu_final is not None:
         t0 = time.perf_counter()
         out["verify"] = verify_sample(work, eq, gpu_final)
