@@ -43,6 +43,7 @@ WORKLOADS = {
     "euler_f64_prec": (wl.EULER_PREC, sw.EULER_F64),
     "euler_f64_flat_large": (wl.EULER_LARGE, sw.EULER_F64_FLAT),
     "euler_f32_flat_prec": (wl.EULER_PREC, sw.EULER_F32_FLAT),
+    "euler_f64_flat_prec": (wl.EULER_PREC, sw.EULER_F64_FLAT),
 }
 
 # algorithmic bytes of the swept working struct per cell (read + write per phase)
