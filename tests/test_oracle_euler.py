@@ -5,7 +5,8 @@ minmod limiter on the stored pressure ratio, four three-point sub-steps per
 step) is checked against the exact Riemann solution of the Sod tube, the
 second-order convergence of a linear acoustic wave, conservation, exact
 symmetries, a constant-state fixed point, the first-order special case that
-a uniform pressure forces, and a 50-digit evaluation on tiny grids.
+a uniform pressure forces, a 50-digit evaluation on tiny grids, and one across
+pressure plateaus where the ratio meets 0/0, x/0 and 0/d.
 """
 import json
 import math
@@ -262,3 +263,99 @@ def test_f32_constant_state_fixed_point():
     q[0], q[1], q[2] = 0.7, 0.3, 2.1
     got, c = oracle.euler_f32(q, np.zeros_like(q), 20, 0.2)
     assert np.array_equal(got, q) and not np.any(c)
+
+
+def _mp_scheme_plateaus(q, steps, lam):
+    """50-digit evaluation of the four sub-steps where pressure differences
+    may vanish exactly.  The ratio Pr = (p[i+1] - p[i]) / (p[i] - p[i-1]) and
+    the limiter then follow the IEEE reading the scheme takes for such
+    cases: an exactly zero difference is +0, so x / 0 is +inf or -inf by the
+    sign of x, 0 / 0 is NaN, and 0 / d is a zero carrying the sign of d;
+    phi(NaN) = phi(+-0) = phi(-inf) = 0 and phi(+inf) = 1, and 1 / (+-0) is
+    +-inf, 1 / (+-inf) is +-0.  Ratios are tagged values here, never floats."""
+    mpmath.mp.dps = 50
+    n = q.shape[1]
+    g, gm1 = mpmath.mpf("1.4"), mpmath.mpf("0.4")
+    lam = mpmath.mpf(lam)
+    Q0 = [[mpmath.mpf(float(q[k, i])) for i in range(n)] for k in range(3)]
+
+    def pressure(U, i):
+        return gm1 * (U[2][i] - U[1][i] ** 2 / U[0][i] / 2)
+
+    def ratio(num, den):
+        if den != 0:
+            return ("zero", 1 if den > 0 else -1) if num == 0 else ("val", num / den)
+        if num == 0:
+            return ("nan", 0)
+        return ("inf", 1 if num > 0 else -1)
+
+    def phi(r):  # phi(Pr)
+        kind, v = r
+        if kind == "val":
+            return min(v, 1) if v > 0 else mpmath.mpf(0)
+        return mpmath.mpf(1) if (kind == "inf" and v > 0) else mpmath.mpf(0)
+
+    def phi_inv(r):  # phi(1 / Pr)
+        kind, v = r
+        if kind == "val":
+            x = 1 / v
+            return min(x, 1) if x > 0 else mpmath.mpf(0)
+        return mpmath.mpf(1) if (kind == "zero" and v > 0) else mpmath.mpf(0)
+
+    def ratios(U):
+        p = [pressure(U, i) for i in range(n)]
+        return [ratio(p[(i + 1) % n] - p[i], p[i] - p[i - 1]) for i in range(n)]
+
+    def flux(U, R, i):  # face between i-1 and i
+        lft = (i - 1) % n
+        a = [U[k][lft] for k in range(3)]
+        b = [U[k][i] for k in range(3)]
+        sl, sr = phi_inv(R[lft]), phi(R[i])
+        ul = [a[k] + sl * (b[k] - a[k]) / 2 for k in range(3)]
+        ur = [b[k] - sr * (b[k] - a[k]) / 2 for k in range(3)]
+
+        def phys(w):
+            v = w[1] / w[0]
+            p = gm1 * (w[2] - w[1] * v / 2)
+            return v, p, mpmath.sqrt(g * p / w[0]), [w[1], w[1] * v + p, (w[2] + p) * v]
+
+        vl, pl, al, fl = phys(ul)
+        vr, pr, ar, fr = phys(ur)
+        s = max(abs(vl) + al, abs(vr) + ar)
+        return [(fl[k] + fr[k]) / 2 - s * (ur[k] - ul[k]) / 2 for k in range(3)]
+
+    kinds = set()
+    for _ in range(steps):
+        for U_is_q0 in (True, False):
+            U = Q0 if U_is_q0 else Q1
+            R = ratios(U)
+            kinds.update((r[0], r[1] if r[0] != "val" else 0) for r in R)
+            F = [flux(U, R, i) for i in range(n)]
+            if U_is_q0:
+                Q1 = [[Q0[k][i] + lam / 2 * (F[i][k] - F[(i + 1) % n][k]) for i in range(n)]
+                      for k in range(3)]
+            else:
+                Q0 = [[Q0[k][i] + lam * (F[i][k] - F[(i + 1) % n][k]) for i in range(n)]
+                      for k in range(3)]
+    return np.array([[float(x) for x in row] for row in Q0]), kinds
+
+
+@pytest.mark.parametrize("steps", [1, 2])
+def test_limiter_on_exactly_vanishing_pressure_differences(steps):
+    """Pressure plateaus at rest make every kind of degenerate ratio occur:
+    0/0 inside a plateau, +x/0 and -x/0 at the first cell of a jump, 0/+d and
+    0/-d right after it.  The oracle must agree with the 50-digit evaluation
+    that treats each case by the reading above; a limiter that took the sign
+    of a zero difference the other way, or phi(+inf) as 0, changes the faces
+    next to the jumps at first order."""
+    n = 16
+    i = np.arange(n)
+    p = np.repeat([1.0, 2.0, 1.5, 3.0], 4)
+    rho = 1.0 + 0.1 * (i % 3)
+    q = _conserved(rho, np.zeros(n), p)
+    got = oracle.euler_f64(q, steps, 0.1)
+    want, kinds = _mp_scheme_plateaus(q, steps, 0.1)
+    for k in (("nan", 0), ("inf", 1), ("inf", -1), ("zero", 1), ("zero", -1)):
+        assert k in kinds, k
+    rel = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    assert rel < 1e-13, rel
