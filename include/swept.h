@@ -126,8 +126,9 @@ size_t sw_state_bytes(int eq, int64_t n_cells);
 size_t sw_workspace_bytes(int eq, int64_t n_cells, int width, int method);
 
 /* Largest triangle width the swept kernels accept for `eq` (set by the LDS
- * a tile needs: (W + 2) cells of working struct plus scratch, within the
- * 160 KiB of LDS of one gfx950 compute unit).  0 for an invalid eq. */
+ * a tile needs: W + 2R cells of working struct plus scratch, within the
+ * 160 KiB of LDS of one gfx950 compute unit), at most 8192.  0 for an
+ * invalid eq. */
 int sw_max_width(int eq);
 
 /* The width swept_solve picks when none is given and the autotuner has
