@@ -1,9 +1,9 @@
 """Randomised GPU properties and the performance claim of the method.
 
 * For random grid sizes that are a multiple of a random valid width, random
-  step counts (remainders included) and random initial states, the swept
-  result equals the classic per-step result bit for bit, in every equation
-  and precision.
+  workgroup sizes, random step counts (remainders included) and random
+  initial states, the swept result equals the classic per-step result bit
+  for bit, in every equation and precision.
 * On the benchmark grids (2^22 cells) the swept rule is faster than the
   classic one-launch-per-step path, for heat and for Euler.
 """
@@ -49,22 +49,27 @@ def _random_state(eq, n, seed):
 def _cases(draw):
     eq = draw(st.sampled_from(EQS))
     step = 2 * sw.radius(eq)
-    w = step * draw(st.integers(1, 128 // step))
-    tiles = draw(st.integers(2, 9))
-    steps = draw(st.integers(0, 3 * w))
+    if draw(st.booleans()):
+        w = step * draw(st.integers(1, 128 // step))
+        tiles = draw(st.integers(2, 9))
+    else:  # the wide tiles of the default launches, compile-time widths included
+        w = draw(st.sampled_from([256, 512, 1024, 2048]))
+        tiles = draw(st.integers(2, 3))
+    steps = draw(st.integers(0, min(3 * w, 700)))
+    threads = draw(st.sampled_from([0, 64, 128, 256, 512]))
     seed = draw(st.integers(0, 2 ** 31 - 1))
-    return eq, w * tiles, w, steps, seed
+    return eq, w * tiles, w, steps, threads, seed
 
 
-@settings(max_examples=40, deadline=None, derandomize=True,
+@settings(max_examples=150, deadline=None, derandomize=True,
           suppress_health_check=[HealthCheck.too_slow])
 @given(_cases())
 def test_random_grids_swept_equals_naive(case):
-    eq, n, w, steps, seed = case
-    announce("property", eq, n, w, steps, seed)
+    eq, n, w, steps, threads, seed = case
+    announce("property", eq, n, w, steps, threads, seed)
     host = _random_state(eq, n, seed)
     dt = 0.25 if eq in (sw.HEAT_F64, sw.HEAT_F32) else 0.1
-    swept = run(eq, host, steps, dt, 1.0, "swept", width=w)
+    swept = run(eq, host, steps, dt, 1.0, "swept", width=w, threads=threads)
     naive = run(eq, host, steps, dt, 1.0, "naive")
     assert np.array_equal(swept, naive), case
 
