@@ -283,3 +283,28 @@ def test_flat_struct_schedule_equals_stepping(n, width):
     q0 = [rng.getrandbits(60) for _ in range(n)]
     for steps in sorted({0, 1, 2, 3, rng.randint(1, width)}):
         assert _swept_flat(q0, 2 * steps, width) == _naive_flat(q0, 2 * steps)
+
+
+@pytest.mark.parametrize("width", [4, 8, 64, 1024])
+def test_structural_facts_of_the_paper(width):
+    """Sec. 4.1: the Up Triangle ends with two values at the centre after W/2
+    sub-steps, and each exchange between neighbouring blocks moves W/2 + 1
+    values: a tile of the next phase reads its W cells and one halo cell per
+    side, W/2 + 1 of them from each of the two tiles of the previous phase
+    that it straddles."""
+    half = width // 2
+    levels = 5 * half
+    lo, hi = sw.sw_phase_interval(1, levels, width, half)
+    assert (lo, hi) == (half - 1, half + 1)          # two centre values at level W/2
+    for k in range(2, sw.sw_phase_count(levels, width) + 1):
+        off_prev = sw.sw_phase_info(k - 1, levels, width)[0]
+        off = sw.sw_phase_info(k, levels, width)[0]
+        assert (off - off_prev) % width == half       # shifted by W/2
+        n = 4 * width
+        t0 = off + width                               # any tile of phase k
+        reads = set(range(t0 - 1, t0 + width + 1))     # W + 2 cells
+        owners = {}
+        for c in reads:
+            owner = ((c - off_prev) % n) // width     # previous-phase tile holding cell c
+            owners[owner] = owners.get(owner, 0) + 1
+        assert sorted(owners.values()) == [half + 1, half + 1]
