@@ -60,7 +60,13 @@ __device__ void copy_out(const BatchProblem &P, int tile)
     }
 }
 
-template <int NT>
+// Tile bodies compiled into a persistent kernel: all of them, or only one
+// heat body.  A kernel holds the registers of its largest body, so a batch
+// of heat problems alone runs a kernel without the Euler bodies and fits
+// twice the workgroups per CU.
+enum Bodies { kAllBodies = 0, kHeatF64Only = 1, kHeatF32Only = 2 };
+
+template <int NT, int BODIES>
 __global__ void __launch_bounds__(NT) k_batch_persistent(BatchTables b)
 {
     extern __shared__ double lds[];
@@ -127,6 +133,11 @@ __global__ void __launch_bounds__(NT) k_batch_persistent(BatchTables b)
             // 512 in four-wave workgroups, 512 and 1024 in eight-wave ones
             constexpr int kWideA = NT >= 512 ? 1024 : 512;
             constexpr int kWideB = NT >= 512 ? 512 : 256;
+            if constexpr (BODIES == kHeatF64Only) {
+                heat_f64_tile<NT>(jb, lds);
+            } else if constexpr (BODIES == kHeatF32Only) {
+                heat_f32_tile<NT>(jb, (float *)lds);
+            } else {
             switch (P.eq) {
             case 0: heat_f64_tile<NT>(jb, lds); break;
             case 1: heat_f32_tile<NT>(jb, (float *)lds); break;
@@ -148,6 +159,7 @@ __global__ void __launch_bounds__(NT) k_batch_persistent(BatchTables b)
                 break;
             case 4: flat_f64_tile<NT>(jb, lds); break;
             default: flat_f32_tile<NT>(jb, lds); break;
+            }
             }
         }
         // publish: every thread's stores reach device scope before the flag
@@ -188,22 +200,47 @@ hipError_t fill(T *p, int64_t count, T v, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int NT>
+hipError_t occupancy_of(int bodies, size_t lds_bytes, int *blocks_per_cu)
+{
+    if (bodies == kHeatF64Only)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            blocks_per_cu, k_batch_persistent<NT, kHeatF64Only>, NT, lds_bytes);
+    if (bodies == kHeatF32Only)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            blocks_per_cu, k_batch_persistent<NT, kHeatF32Only>, NT, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks_per_cu, k_batch_persistent<NT, kAllBodies>, NT, lds_bytes);
+}
+
+template <int NT>
+void launch_persistent(int bodies, int blocks, size_t lds_bytes, hipStream_t s,
+                       const BatchTables &t)
+{
+    if (bodies == kHeatF64Only)
+        hipLaunchKernelGGL((k_batch_persistent<NT, kHeatF64Only>), dim3((unsigned)blocks), dim3(NT),
+                           lds_bytes, s, t);
+    else if (bodies == kHeatF32Only)
+        hipLaunchKernelGGL((k_batch_persistent<NT, kHeatF32Only>), dim3((unsigned)blocks), dim3(NT),
+                           lds_bytes, s, t);
+    else
+        hipLaunchKernelGGL((k_batch_persistent<NT, kAllBodies>), dim3((unsigned)blocks), dim3(NT),
+                           lds_bytes, s, t);
+}
+
 } // namespace
 
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s) { return fill(p, count, v, s); }
 hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s) { return fill(p, count, v, s); }
 
-hipError_t batch_occupancy(size_t lds_bytes, int threads, int *blocks_per_cu)
+hipError_t batch_occupancy(size_t lds_bytes, int threads, int bodies, int *blocks_per_cu)
 {
-    if (threads == 512)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            blocks_per_cu, k_batch_persistent<512>, 512, lds_bytes);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_persistent<256>,
-                                                        256, lds_bytes);
+    return threads == 512 ? occupancy_of<512>(bodies, lds_bytes, blocks_per_cu)
+                          : occupancy_of<256>(bodies, lds_bytes, blocks_per_cu);
 }
 
 hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, int threads,
-                        size_t lds_bytes, hipStream_t s)
+                        int bodies, size_t lds_bytes, hipStream_t s)
 {
     const int64_t rb = (n_flags + 255) / 256;
     const unsigned reset_blocks = (unsigned)(rb < 1 ? 1 : (rb > 4096 ? 4096 : rb));
@@ -213,11 +250,9 @@ hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, int t
     if (e != hipSuccess)
         return e;
     if (threads == 512)
-        hipLaunchKernelGGL(k_batch_persistent<512>, dim3((unsigned)blocks), dim3(512), lds_bytes,
-                           s, t);
+        launch_persistent<512>(bodies, blocks, lds_bytes, s, t);
     else
-        hipLaunchKernelGGL(k_batch_persistent<256>, dim3((unsigned)blocks), dim3(256), lds_bytes,
-                           s, t);
+        launch_persistent<256>(bodies, blocks, lds_bytes, s, t);
     return hipGetLastError();
 }
 

@@ -34,9 +34,10 @@
 
 namespace sw {
 
-hipError_t batch_occupancy(size_t lds_bytes, int threads, int *blocks_per_cu);
+// bodies: 0 every tile body, 1 heat binary64 only, 2 heat binary32 only
+hipError_t batch_occupancy(size_t lds_bytes, int threads, int bodies, int *blocks_per_cu);
 hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, int threads,
-                        size_t lds_bytes, hipStream_t s);
+                        int bodies, size_t lds_bytes, hipStream_t s);
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s);
 hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s);
 
@@ -221,6 +222,7 @@ struct sw_batch_impl {
     int64_t flags = 0;
     int blocks = 0;
     int threads = 256;
+    int bodies = 0;
     std::vector<int> widths;
 };
 
@@ -460,8 +462,20 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
         }
 
     sw_batch_impl *b = new sw_batch_impl();
+    // a batch of heat problems of one precision runs the kernel compiled with
+    // that body alone (fewer registers, more resident workgroups)
+    int bodies = 0;
+    {
+        bool all64 = true, all32 = true;
+        for (int i = 0; i < n_problems; ++i) {
+            all64 = all64 && problems[i].eq == SW_HEAT_F64;
+            all32 = all32 && problems[i].eq == SW_HEAT_F32;
+        }
+        bodies = all64 ? 1 : (all32 ? 2 : 0);
+    }
     b->device = dev;
     b->threads = threads;
+    b->bodies = bodies;
     b->widths = widths;
     b->items = items;
     b->flags = flags;
@@ -507,7 +521,7 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
 
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        sw::batch_occupancy(max_lds, threads, &per_cu) != hipSuccess || per_cu < 1) {
+        sw::batch_occupancy(max_lds, threads, bodies, &per_cu) != hipSuccess || per_cu < 1) {
         (void)hipGetLastError();
         free_batch(b);
         return fail(SW_ERR_HIP, "batch occupancy query failed (LDS %zu bytes)", max_lds);
@@ -525,7 +539,7 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
     if (e == hipSuccess)
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = sw::batch_launch(t, flags, b->blocks, threads, max_lds, cap);
+        hipError_t le = sw::batch_launch(t, flags, b->blocks, threads, bodies, max_lds, cap);
         e = hipStreamEndCapture(cap, &b->graph);
         if (le != hipSuccess)
             e = le;

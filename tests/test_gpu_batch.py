@@ -277,3 +277,34 @@ def test_swept_solve_captured_in_a_graph(eq):
         torch.cuda.synchronize()
         eager = run(eq, eager, steps, dt, 1.0, "swept")
         assert np.array_equal(state.cpu().numpy(), eager), rep
+
+
+@pytest.mark.parametrize("eq", [sw.HEAT_F64, sw.HEAT_F32])
+@pytest.mark.parametrize("threads", [0, 512])
+def test_heat_only_batch_runs_the_heat_kernel_and_matches(eq, threads):
+    """A batch whose problems are all heat of one precision runs the
+    persistent kernel compiled with that body alone; every problem (one-step
+    copy-out items, ragged widths and remainders included) still equals its
+    own swept solve and the oracle bit for bit."""
+    import torch
+    specs = [(eq, 2048, 1, 256, 61),      # single phase: copy-out items
+             (eq, 1000, 77, 40, 62),      # ragged width
+             (eq, 3 * 2048, 1500, 2048, 63),
+             (eq, 4096, 333, 1024, 64),
+             (eq, 4098, 100, 2, 65)]      # one level per phase
+    tensors, hosts, probs = _problems(specs)
+    announce("heat-only batch", eq, "threads", threads)
+    b = sw.Batch(probs, threads=threads)
+    stream = torch.cuda.current_stream().cuda_stream
+    b.run(stream)
+    assert b.wait(stream) == sw.SW_OK, sw.last_error()
+    for (e, n, steps, width, seed), t, host in zip(specs, tensors, hosts):
+        got = t.cpu().numpy()
+        alone = run(e, host, steps, 0.25, 1.0, "swept", width=width)
+        assert np.array_equal(got, alone), (n, steps, width)
+        if e == sw.HEAT_F64:
+            assert np.array_equal(got[0], oracle.heat_f64(host[0], steps, 0.25))
+        else:
+            u, c = oracle.heat_f32(host[0], host[1], steps, 0.25)
+            assert np.array_equal(got[0], u) and np.array_equal(got[1], c)
+    b.close()
