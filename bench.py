@@ -1,11 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the swept-rule hot path on one MI355X.
 
-One benchmark step is one full solve of the workload through the C ABI
-(``swept_solve``): every phase of the swept schedule -- Up Triangle,
-Diamonds, Down Triangle -- over the whole grid for all its time steps.  The
-default workload is the 1D heat equation (FTCS, binary64) on 2^22 periodic
-cells, r = 1/4, seeded random-mode initial condition, 20000 time steps.
+One benchmark step is one full solve of the workload through the C ABI:
+every phase of the swept schedule -- Up Triangle, Diamonds, Down Triangle --
+over the whole grid for all its time steps.  Two schedules of the same
+phases exist: one kernel launch per phase (``swept_solve``), or one
+persistent launch that overlaps consecutive phases tile by tile (the batched
+launch with the single problem, ``sw_batch_run``).  By default the heat
+workloads use the persistent launch and the Euler workloads the phase
+launches, the faster of the two for each on MI355X.  The default workload is
+the 1D heat equation (FTCS, binary64) on 2^22 periodic cells, r = 1/4,
+seeded random-mode initial condition, 20000 time steps.
 
 Prints ONE JSON line: the swept throughput in cell-updates/s (value), the
 classic one-launch-per-step throughput on the same workload, the roofline
@@ -71,6 +76,8 @@ LDS_PEAK_GBS = 256 * 128 * 2.4e9 / 1e9
 # one write (binary32: plus the compensation read and write)
 LDS_BYTES_PER_UPDATE = {sw.HEAT_F64: 32, sw.HEAT_F32: 24}
 PROFILES = os.path.join(ROOT, "profiles")
+# the persistent launch of a heat-only batch (its kernel compiles only the heat body)
+PERSISTENT_SOURCES = ["batch.hip", "batch.h", "tile_heat.h", "geom.h", "tile_job.h"]
 KERNEL_SOURCES = {
     sw.HEAT_F64: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h"],
     sw.HEAT_F32: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h"],
@@ -81,27 +88,30 @@ KERNEL_SOURCES = {
 }
 
 
-def kernel_source_hash(eq) -> str:
-    """sha256 of the sources of the swept phase kernel of `eq`."""
+def kernel_source_hash(eq, schedule="phases") -> str:
+    """sha256 of the sources of the swept kernel of `eq` under `schedule`."""
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES[eq]:
+    for name in (PERSISTENT_SOURCES if schedule == "persistent" else KERNEL_SOURCES[eq]):
         with open(os.path.join(ROOT, "paper_1811_08282_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_counters(work, eq, width, threads):
-    """Per-launch hardware counters of the swept phase kernel taken with
-    rocprofv3 on this workload (profiles/<workload>_phase_counters.txt), or None when
-    absent or taken on other kernel sources or another launch (width, workgroup size)."""
+def measured_counters(work, eq, width, threads, schedule="phases"):
+    """Per-launch hardware counters of the swept kernel taken with rocprofv3 on
+    this workload (profiles/<workload>_phase_counters.txt for the phase
+    launches, <workload>_persistent_counters.txt for the persistent launch),
+    or None when absent or taken on other kernel sources or another launch
+    (width, workgroup size)."""
     layout = "_flattened" if eq in (sw.EULER_F64_FLAT, sw.EULER_F32_FLAT) else ""
-    path = os.path.join(PROFILES, f"{work.name}{layout}_phase_counters.txt")
+    kind = "persistent" if schedule == "persistent" else "phase"
+    path = os.path.join(PROFILES, f"{work.name}{layout}_{kind}_counters.txt")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if (rec.get("source_sha256") != kernel_source_hash(eq) or rec.get("width") != width
+    if (rec.get("source_sha256") != kernel_source_hash(eq, schedule) or rec.get("width") != width
             or rec.get("threads") != threads):
         return None
     return rec
@@ -141,6 +151,57 @@ def time_solves(torch, eq, state0, work, method, width, reps, warmup, threads=0)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     return start.elapsed_time(stop) / reps, wall / reps
+
+
+def _batch_problem(eq, dev, work, width):
+    return dict(eq=eq, width=width, n_cells=work.n, n_steps=work.steps, dt=work.dt, dx=work.dx,
+                d_state=dev.data_ptr())
+
+
+def time_persistent(torch, eq, state0, work, width, threads, reps, warmup):
+    """Mean ms per solve over `reps` persistent launches of the batch holding
+    the single problem (events on torch's current stream, the launch stream);
+    also returns the width the batch chose."""
+    dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
+    torch.cuda.synchronize()
+    b = sw.Batch([_batch_problem(eq, dev, work, width)], threads=threads)
+    stream = torch.cuda.current_stream()
+    handle = stream.cuda_stream
+    for _ in range(warmup):
+        b.run(handle)
+    if b.wait(handle) != sw.SW_OK:
+        raise RuntimeError(sw.last_error())
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run(handle)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    if b.wait(handle) != sw.SW_OK:
+        raise RuntimeError(sw.last_error())
+    chosen = b.width(0)
+    b.close()
+    return start.elapsed_time(stop) / reps, wall / reps, chosen
+
+
+def solve_once(torch, eq, state0, work, width, threads, schedule):
+    """One solve from state0 on the given schedule; returns the device tensor."""
+    dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
+    if schedule == "persistent":
+        torch.cuda.synchronize()
+        b = sw.Batch([_batch_problem(eq, dev, work, width)], threads=threads)
+        handle = torch.cuda.current_stream().cuda_stream
+        b.run(handle)
+        if b.wait(handle) != sw.SW_OK:
+            raise RuntimeError(sw.last_error())
+        b.close()
+    else:
+        sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width,
+                 threads=threads)
+    return dev
 
 
 def _rel(a, b):
@@ -319,7 +380,10 @@ def main() -> int:
     ap.add_argument("--workload", default="heat_f64_large", choices=sorted(WORKLOADS))
     ap.add_argument("--width", type=int, default=0, help="triangle width (0: library choice)")
     ap.add_argument("--threads", type=int, default=0,
-                    help="workgroup size of the swept phases (0: library choice)")
+                    help="workgroup size of the swept kernel (0: library choice)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "phases", "persistent"],
+                    help="one launch per phase, or one persistent launch per solve "
+                         "(auto: persistent for heat, phases for Euler)")
     ap.add_argument("--naive-reps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -350,16 +414,25 @@ def main() -> int:
         return 0
     work, eq = WORKLOADS[args.workload]
     sw.load()
-    width = args.width or sw.sw_default_width(eq, work.n)
-    threads = args.threads or sw.sw_default_threads(eq, width)
-    final_level = work.steps * sw.substeps(eq)
-    phases = sw.sw_phase_count(final_level, width, sw.radius(eq))
+    schedule = args.schedule
+    if schedule == "auto":
+        schedule = "persistent" if eq in (sw.HEAT_F64, sw.HEAT_F32) else "phases"
     state0 = pack_state(eq, wl.initial_state(work))
     updates = work.n * work.steps
-
-    log(f"[bench] workload {work.name} eq={eq} W={width} threads={threads} phases={phases}")
-    ms, wall_ms = time_solves(torch, eq, state0, work, "swept", width, args.steps, args.warmup,
-                              threads)
+    if schedule == "persistent":
+        threads = args.threads or 256
+        ms, wall_ms, width = time_persistent(torch, eq, state0, work, args.width, threads,
+                                             args.steps, args.warmup)
+    else:
+        width = args.width or sw.sw_default_width(eq, work.n)
+        threads = args.threads or sw.sw_default_threads(eq, width)
+    final_level = work.steps * sw.substeps(eq)
+    phases = sw.sw_phase_count(final_level, width, sw.radius(eq))
+    log(f"[bench] workload {work.name} eq={eq} W={width} threads={threads} phases={phases} "
+        f"schedule={schedule}")
+    if schedule == "phases":
+        ms, wall_ms = time_solves(torch, eq, state0, work, "swept", width, args.steps,
+                                  args.warmup, threads)
     log(f"[bench] swept {ms:.3f} ms/solve ({updates / ms * 1e3:.4g} cell-updates/s)")
     naive_ms = float("nan")
     if not args.no_naive:
@@ -370,30 +443,33 @@ def main() -> int:
     # to and from the host; reported beside the HBM-resident figure only
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
-    sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width, threads=threads)
+    dev = solve_once(torch, eq, state0, work, width, threads, schedule)
     host_final = dev.cpu().numpy()
     paper_ms = (time.perf_counter() - t0) * 1e3
     del dev, host_final
 
     value = updates / (ms * 1e-3)
     naive_value = updates / (naive_ms * 1e-3) if naive_ms == naive_ms else None
-    launch_ms = ms / phases
+    # dominant kernel: the swept phase kernel (one launch per phase) or the
+    # persistent kernel (one launch per solve, every phase inside)
+    launches = 1 if schedule == "persistent" else phases
+    launch_ms = ms / launches
     tiles = work.n // width
-    # dominant kernel: the swept phase kernel (all launches of a swept solve)
-    alg_bytes = tiles * ((width + 2 * sw.radius(eq)) + width) * STRUCT_BYTES[eq]
+    alg_bytes = (phases // launches) * tiles * ((width + 2 * sw.radius(eq)) + width) \
+        * STRUCT_BYTES[eq]
     achieved_gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
     hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes}
-    counters = measured_counters(work, eq, width, threads)
+    counters = measured_counters(work, eq, width, threads, schedule)
     traffic = counters.get("hbm_bytes_per_launch") if counters else None
     ops = OPS_PER_UPDATE[eq]
     achieved = value * ops / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                "ops_per_cell_update": ops, "flops_per_launch": updates * ops / phases,
-                "kernel": "swept phase kernel", "launch_ms": launch_ms,
-                "launches_per_step": phases, "hbm": hbm}
+                "ops_per_cell_update": ops, "flops_per_launch": updates * ops / launches,
+                "kernel": ("persistent swept kernel (heat body alone)" if schedule == "persistent"
+                           else "swept phase kernel"),
+                "launch_ms": launch_ms, "launches_per_step": launches, "hbm": hbm}
     if eq in LDS_BYTES_PER_UPDATE:
         lds_gbs = value * LDS_BYTES_PER_UPDATE[eq] / 1e9
         roofline["lds"] = {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
@@ -403,7 +479,7 @@ def main() -> int:
         # LDS bytes the SQ counters saw (64-byte units of the load and store
         # bandwidth counters), per cell-update and per second of launch time
         lds_bytes = counters["lds_load_bytes_per_launch"] + counters["lds_store_bytes_per_launch"]
-        measured = {"bytes_per_cell_update": lds_bytes / (updates / phases),
+        measured = {"bytes_per_cell_update": lds_bytes / (updates / launches),
                     "achieved": lds_bytes / (launch_ms * 1e-3) / 1e9, "peak": LDS_PEAK_GBS,
                     "unit": "GB/s"}
         measured["frac"] = measured["achieved"] / LDS_PEAK_GBS
@@ -418,7 +494,7 @@ def main() -> int:
         # rate (one wave instruction per clock per CU)
         rate = counters["valu_insts_per_launch"] / (launch_ms * 1e-3)
         roofline["valu_issue"] = {
-            "insts_per_cell_update": counters["valu_insts_per_launch"] * 64 / (updates / phases),
+            "insts_per_cell_update": counters["valu_insts_per_launch"] * 64 / (updates / launches),
             "achieved": rate / 1e9, "peak": 256 * 2.4, "unit": "G wave-insts/s",
             "frac": rate / (256 * 2.4e9)}
     out = {
@@ -436,7 +512,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": work.name + ("_flattened" if eq in (sw.EULER_F64_FLAT, sw.EULER_F32_FLAT) else ""),
                    "n_cells": work.n, "time_steps": work.steps, "width": width,
-                   "threads": threads,
+                   "threads": threads, "schedule": schedule, "phases": phases,
                    "method": "swept", "parallelism": "single-gpu"},
         "naive": {"value": naive_value, "ms_per_step": naive_ms,
                   "hbm_roofline_value": HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]},
@@ -451,9 +527,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         # one more solve from the same input, outside the timed region, for
         # the sampled check against the oracle in the CPU leg
-        dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
-        sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width,
-                 threads=threads)
+        dev = solve_once(torch, eq, state0, work, width, threads, schedule)
         torch.cuda.synchronize()
         final = dev.cpu().numpy()
         del dev

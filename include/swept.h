@@ -229,9 +229,12 @@ void sw_tune_clear(void);
  * reports SW_ERR_HIP from sw_batch_wait.  The persistent kernel runs
  * 256-thread workgroups unless sw_batch_opts asks for 512 (the batch
  * autotuner tries both); a problem without a width and without a tuned one
- * takes the largest valid width up to 1024 (heat binary32 2048, lengthened
- * Euler 512), and the LDS of the widest tile sets the resident workgroups
- * per CU of the whole batch. */
+ * takes the largest valid width up to 2048 for heat, 1024 for flattened
+ * Euler and 512 for lengthened Euler, and the LDS of the widest tile sets
+ * the resident workgroups per CU of the whole batch.  A batch whose problems
+ * are all heat of one precision runs a kernel compiled with that tile body
+ * alone (fewer registers, twice the resident workgroups); a single heat
+ * problem in such a batch is one launch that overlaps the phases. */
 typedef struct {
     int eq;          /* sw_equation                                          */
     int width;       /* triangle width, 0 = tuned width, else library choice */
@@ -260,7 +263,8 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
 int sw_batch_run(sw_batch batch, sw_stream stream);
 
 /* Synchronise `stream` and report whether the last run completed
- * (SW_ERR_HIP if a dependency wait exceeded its bound). */
+ * (SW_ERR_HIP if a dependency wait exceeded its bound; SW_OK before any
+ * run). */
 int sw_batch_wait(sw_batch batch, sw_stream stream);
 
 /* Work items, resident workgroups and working-array bytes of a batch. */

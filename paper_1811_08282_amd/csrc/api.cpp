@@ -88,12 +88,14 @@ int preferred_width(int eq)
 }
 
 // the same for the batch kernel, whose workgroups have 256 threads:
-// lengthened Euler is best at 512 there
+// lengthened Euler is best at 512 there, heat at 2048 (a phase of a lone
+// 2^22-cell heat problem is then 2048 items, which the persistent launch
+// overlaps with the next phase's)
 int preferred_batch_width(int eq)
 {
-    if (eq == SW_HEAT_F32)
+    if (!is_euler(eq))
         return 2048;
-    return (is_euler(eq) && !is_flat(eq)) ? 512 : 1024;
+    return is_flat(eq) ? 1024 : 512;
 }
 
 // workgroup size of a swept phase when the caller gives none: Euler tiles of

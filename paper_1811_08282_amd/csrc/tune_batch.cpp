@@ -500,10 +500,13 @@ int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_o
         arr += 2 * copy;
     }
     char *tb = (char *)b->tables;
+    // the ticket and the status word start at zero, so that sw_batch_wait
+    // before any run reports success (each run resets them on the device)
     if (hipMemcpy(tb, hp.data(), sizeof(sw::BatchProblem) * n_problems, hipMemcpyHostToDevice) !=
             hipSuccess ||
         (!segs.empty() && hipMemcpy(tb + off_seg, segs.data(), sizeof(sw::BatchSegment) * segs.size(),
-                                    hipMemcpyHostToDevice) != hipSuccess)) {
+                                    hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemset(tb + off_ticket, 0, off_flags - off_ticket) != hipSuccess) {
         free_batch(b);
         return fail(SW_ERR_HIP, "uploading batch tables failed");
     }
