@@ -129,37 +129,37 @@ __global__ void __launch_bounds__(NT) k_batch_persistent(BatchTables b)
             jb.first = (k == 1);
             jb.last = (k == P.phases) && !P.single_phase;
             jb.final_level = P.final_level;
-            // compile-time LDS offsets for the common Euler widths: 256 and
-            // 512 in four-wave workgroups, 512 and 1024 in eight-wave ones
-            constexpr int kWideA = NT >= 512 ? 1024 : 512;
-            constexpr int kWideB = NT >= 512 ? 512 : 256;
             if constexpr (BODIES == kHeatF64Only) {
                 heat_f64_tile<NT>(jb, lds);
             } else if constexpr (BODIES == kHeatF32Only) {
                 heat_f32_tile<NT>(jb, (float *)lds);
             } else {
-            switch (P.eq) {
-            case 0: heat_f64_tile<NT>(jb, lds); break;
-            case 1: heat_f32_tile<NT>(jb, (float *)lds); break;
-            case 2:
-                if (P.w == kWideA)
-                    euler_f64_tile<NT, kWideA>(jb, lds);
-                else if (P.w == kWideB)
-                    euler_f64_tile<NT, kWideB>(jb, lds);
-                else
-                    euler_f64_tile<NT>(jb, lds);
-                break;
-            case 3:
-                if (P.w == kWideA)
-                    euler_f32_tile<NT, kWideA>(jb, lds);
-                else if (P.w == kWideB)
-                    euler_f32_tile<NT, kWideB>(jb, lds);
-                else
-                    euler_f32_tile<NT>(jb, lds);
-                break;
-            case 4: flat_f64_tile<NT>(jb, lds); break;
-            default: flat_f32_tile<NT>(jb, lds); break;
-            }
+                // compile-time LDS offsets for the common Euler widths: 256
+                // and 512 in four-wave workgroups, 512 and 1024 in eight-wave
+                constexpr int kWideA = NT >= 512 ? 1024 : 512;
+                constexpr int kWideB = NT >= 512 ? 512 : 256;
+                switch (P.eq) {
+                case 0: heat_f64_tile<NT>(jb, lds); break;
+                case 1: heat_f32_tile<NT>(jb, (float *)lds); break;
+                case 2:
+                    if (P.w == kWideA)
+                        euler_f64_tile<NT, kWideA>(jb, lds);
+                    else if (P.w == kWideB)
+                        euler_f64_tile<NT, kWideB>(jb, lds);
+                    else
+                        euler_f64_tile<NT>(jb, lds);
+                    break;
+                case 3:
+                    if (P.w == kWideA)
+                        euler_f32_tile<NT, kWideA>(jb, lds);
+                    else if (P.w == kWideB)
+                        euler_f32_tile<NT, kWideB>(jb, lds);
+                    else
+                        euler_f32_tile<NT>(jb, lds);
+                    break;
+                case 4: flat_f64_tile<NT>(jb, lds); break;
+                default: flat_f32_tile<NT>(jb, lds); break;
+                }
             }
         }
         // publish: every thread's stores reach device scope before the flag
