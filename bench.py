@@ -434,6 +434,17 @@ def main() -> int:
         ms, wall_ms = time_solves(torch, eq, state0, work, "swept", width, args.steps,
                                   args.warmup, threads)
     log(f"[bench] swept {ms:.3f} ms/solve ({updates / ms * 1e3:.4g} cell-updates/s)")
+    phase_launches = None
+    if schedule == "persistent":
+        # the same solve through swept_solve (one launch per phase), for reference
+        pw = sw.sw_default_width(eq, work.n)
+        pt = sw.sw_default_threads(eq, pw)
+        pms, _ = time_solves(torch, eq, state0, work, "swept", pw, args.steps, args.warmup, pt)
+        phase_launches = {"value": updates / (pms * 1e-3), "ms_per_step": pms, "width": pw,
+                          "threads": pt, "launches_per_step": sw.sw_phase_count(
+                              work.steps * sw.substeps(eq), pw, sw.radius(eq))}
+        log(f"[bench] swept, one launch per phase {pms:.3f} ms/solve "
+            f"({updates / pms * 1e3:.4g} cell-updates/s)")
     naive_ms = float("nan")
     if not args.no_naive:
         naive_ms, _ = time_solves(torch, eq, state0, work, "naive", 0, args.naive_reps, 1)
@@ -514,6 +525,7 @@ def main() -> int:
                    "n_cells": work.n, "time_steps": work.steps, "width": width,
                    "threads": threads, "schedule": schedule, "phases": phases,
                    "method": "swept", "parallelism": "single-gpu"},
+        "swept_phase_launches": phase_launches,
         "naive": {"value": naive_value, "ms_per_step": naive_ms,
                   "hbm_roofline_value": HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]},
         "swept_over_naive": value / naive_value if naive_value else None,
