@@ -513,6 +513,13 @@ def main() -> int:
             "insts_per_cell_update": counters["valu_insts_per_launch"] * 64 / (updates / launches),
             "achieved": rate / 1e9, "peak": 256 * 2.4, "unit": "G wave-insts/s",
             "frac": rate / (256 * 2.4e9)}
+    # with a counter profile, the unit nearer its ceiling binds (binary32 heat
+    # issues VALU instructions at 94 % of the chip's rate while its LDS port
+    # runs at 73 %)
+    lds_meas = roofline.get("lds", {}).get("measured")
+    if "valu_issue" in roofline and lds_meas:
+        roofline["binding_unit"] = ("valu" if roofline["valu_issue"]["frac"] > lds_meas["frac"]
+                                    else "lds")
     out = {
         "metric": METRIC,
         "value": value,
