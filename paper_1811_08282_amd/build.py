@@ -18,9 +18,6 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswept.so")
 SOURCES = ["api.cpp", "tune_batch.cpp", "heat.hip", "euler.hip", "euler_flat.hip", "batch.hip"]
-# standalone LDS throughput probe (not linked into the library)
-PROBE_SOURCE = "lds_probe.hip"
-PROBE = os.path.join(HERE, "lds_probe")
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -52,22 +49,7 @@ def build(verbose: bool = False) -> str:
     if verbose and noise:
         sys.stderr.write("\n".join(noise) + "\n")
     os.replace(tmp, LIB)
-    build_probe(verbose)
     return LIB
-
-
-def build_probe(verbose: bool = False) -> str:
-    flags = [f for f in HIP_FLAGS if f not in ("-shared", "-fPIC")]
-    tmp = PROBE + ".tmp"
-    cmd = [hipcc(), *flags, "-o", tmp, os.path.join(CSRC, PROBE_SOURCE)]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    proc = subprocess.run(cmd, capture_output=True, text=True)
-    if proc.returncode != 0:
-        sys.stderr.write(proc.stdout + proc.stderr)
-        raise RuntimeError("hipcc failed building lds_probe")
-    os.replace(tmp, PROBE)
-    return PROBE
 
 
 if __name__ == "__main__":
