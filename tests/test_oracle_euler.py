@@ -379,3 +379,93 @@ def test_f32_compensated_accumulation_on_a_limiter_free_flow():
     rel = np.max(np.abs(got[0] - ref[0])) / np.max(np.abs(ref[0]))
     assert rel < 1e-6, rel
     assert np.any(c[0])  # the compensation is in use
+
+
+# ---- binary32 path: placement of the binary64 islands -------------------------------
+
+def _high_mach_ic(n=64, u=100.0, p0=1.0, dp=0.01, drho=0.5):
+    """Smooth flow at Mach ~85 (u = 100, a ~ 1.2): the kinetic energy is
+    ~5000 times the internal one, so E - (m u)/2 loses about 12 of binary32's
+    24 bits.  Density and pressure vary, so the limiter acts."""
+    j = np.arange(n)
+    rho = 1.0 + drho * np.sin(2 * np.pi * j / n)
+    p = p0 * (1.0 + dp * np.sin(2 * np.pi * 3 * j / n + 1.0))
+    m = rho * u
+    e = p / 0.4 + 0.5 * rho * u * u
+    return np.array([rho, m, e]).astype(np.float32)
+
+
+def _one_step_increment_error(euler_f32, q32, lam):
+    """rel_inf, per variable, of the binary32 path's one-step increment against
+    the binary64 increment from the same (binary32) state.  lam is so small
+    that no stored value changes: the compensated update leaves the whole
+    increment, negated, in the compensation, and the predicted state equals
+    the state, so both pressure-ratio sub-steps see the exact pressures of the
+    stored binary32 values -- the ones the binary64 run sees."""
+    q64 = q32.astype(np.float64)
+    ref = oracle.euler_f64(q64, 1, lam) - q64
+    q, c = euler_f32(q32, np.zeros_like(q32), 1, lam)
+    assert np.array_equal(q, q32)
+    inc = -c.astype(np.float64)
+    return [float(np.max(np.abs(inc[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in range(3)]
+
+
+_ISLAND_BOUND = 1e-4
+
+
+def test_f32_binary64_islands_on_a_high_mach_flow():
+    """The binary32 path recovers velocity, pressure and sound speed, forms the
+    pressure ratio and the limiter value in binary64.  On a flow where the
+    internal energy is a small difference of large binary32 numbers that
+    recovery is exact to binary64 rounding, so the one-step increment of the
+    binary32 path matches binary64 up to the rounding of its binary32 flux
+    arithmetic (measured ~5e-6); a binary32 recovery puts errors of ~1e-3 of
+    the pressure into every ratio and misses by ~0.2
+    (test_planted_binary32_recovery_fails_the_island_pin)."""
+    q32 = _high_mach_ic()
+    errs = _one_step_increment_error(oracle.euler_f32, q32, 1e-11)
+    assert max(errs) < _ISLAND_BOUND, errs
+
+
+def _mutant_oracle(tmp_path):
+    """The oracle rebuilt with its binary32 recovery (pressure, velocity, sound
+    speed, limiter) evaluated in binary32: a planted mistake."""
+    import ctypes
+    import subprocess
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
+    a = src.index("static double pres32(")
+    b = src.index("static void pr_stage32(")
+    body = src[a:b]
+    for token in ("double", "GM1 *", "GAMMA *", "0.5 *", "sqrt(", "limiter64(1.0 /", "limiter64(prb)"):
+        assert token in body, token
+    body = (body.replace("double", "float").replace("GM1 *", "0.4f *").replace("GAMMA *", "1.4f *")
+            .replace("0.5 *", "0.5f *").replace("sqrt(", "sqrtf(")
+            .replace("limiter64(1.0 /", "limiter32(1.0f /").replace("limiter64(prb)", "limiter32(prb)"))
+    body = ("static float limiter32(float q)\n{\n    if (q > 0.0f)\n        return q < 1.0f ? q : 1.0f;"
+            "\n    return 0.0f;\n}\n\n" + body)
+    path = tmp_path / "oracle_f32_recovery.c"
+    path.write_text(src[:a] + body + src[b:])
+    lib = str(tmp_path / "liboracle_f32_recovery.so")
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-fno-fast-math", "-fexcess-precision=standard", "-o", lib, str(path), "-lm"],
+                   check=True)
+    mut = ctypes.CDLL(lib)
+    vp = ctypes.c_void_p
+    mut.oracle_euler_f32.argtypes = [vp] * 6 + [ctypes.c_int64, ctypes.c_int64, ctypes.c_float,
+                                                ctypes.c_int]
+
+    def euler_f32(q0, c0, steps, lam):
+        q = np.array(q0, np.float32, copy=True, order="C")
+        c = np.array(c0, np.float32, copy=True, order="C")
+        ptrs = [x.ctypes.data for x in (q[0], q[1], q[2], c[0], c[1], c[2])]
+        assert mut.oracle_euler_f32(*ptrs, q.shape[1], steps, float(np.float32(lam)), 1) == 0
+        return q, c
+    return euler_f32
+
+
+def test_planted_binary32_recovery_fails_the_island_pin(tmp_path):
+    """The island pin has teeth: the same oracle with the recovery in binary32
+    misses the bound by more than two orders of magnitude."""
+    mutant = _mutant_oracle(tmp_path)
+    errs = _one_step_increment_error(mutant, _high_mach_ic(), 1e-11)
+    assert min(errs) > 100 * _ISLAND_BOUND, errs
