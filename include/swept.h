@@ -239,7 +239,7 @@ typedef struct {
     int eq;          /* sw_equation                                          */
     int width;       /* triangle width, 0 = tuned width, else library choice */
     int64_t n_cells; /* >= 4; n_cells / width <= 2^31 - 1                     */
-    int64_t n_steps; /* >= 0                                                 */
+    int64_t n_steps; /* >= 0; at most 2^31 - 2 swept phases (K above)        */
     double dt, dx;   /* finite, > 0                                          */
     void *d_state;   /* device state buffer laid out as for swept_solve; the
                         problems' buffers must not overlap                   */
@@ -253,9 +253,46 @@ typedef struct {
 
 typedef struct sw_batch_impl *sw_batch;
 
-/* Validate the problems, allocate every problem's working arrays and the
- * work tables on the current device, and capture the launch into a graph.
- * Synchronous; must not be called during stream capture.  opts may be NULL. */
+/* Bytes of device workspace swept_solve_batch needs for this problem list
+ * (host only; no HIP call): a 256-byte header (ticket and status word), the
+ * problem table (one entry per problem), one 32-bit completion flag per tile
+ * and every problem's two copies of its working arrays (sw_workspace_bytes
+ * of the swept method).  A problem given with width 0 takes its tuned or
+ * default width here exactly as in swept_solve_batch, so both calls must see
+ * the same recorded widths.  0 for an invalid list (message in
+ * sw_last_error). */
+size_t sw_batch_workspace_bytes(int n_problems, const sw_problem *problems);
+
+/* Advance every problem of the list by its n_steps in ONE persistent launch
+ * (Sec. 4.1 applied to many grids at once) in a workspace the caller owns:
+ * d_ws is device memory of the current device, 256-byte aligned, at least
+ * sw_batch_workspace_bytes() long, not used by any other call in flight.
+ * The call plans the batch on the host and enqueues on `stream` the upload
+ * of the problem table (kernels carrying it in their launch arguments), a
+ * reset kernel and the persistent kernel.  It allocates nothing, does not
+ * wait for the device, and may be captured into a graph: each replay
+ * recomputes the batch from the states as they are then.  The problems'
+ * state buffers are read and written as by swept_solve; their contents after
+ * the launch equal swept_solve of each problem with the same width.
+ * SW_ERR_ARG for an invalid list, a NULL or misaligned d_ws, or ws_bytes
+ * below what the list needs (all checked before any HIP call).  A dependency
+ * wait that exceeds its bound (10 s) aborts the launch; sw_batch_check
+ * reports it.  swept_solve_batch_ex takes the launch options of
+ * sw_batch_opts (NULL = defaults: 256-thread workgroups, occupancy limit). */
+int swept_solve_batch(int n_problems, const sw_problem *problems, void *d_ws, size_t ws_bytes,
+                      sw_stream stream);
+int swept_solve_batch_ex(int n_problems, const sw_problem *problems, const sw_batch_opts *opts,
+                         void *d_ws, size_t ws_bytes, sw_stream stream);
+
+/* Synchronise `stream` and report whether the last launch that used the
+ * workspace d_ws completed (SW_ERR_HIP if a dependency wait exceeded its
+ * bound).  Reads the status word of the workspace header. */
+int sw_batch_check(const void *d_ws, sw_stream stream);
+
+/* Validate the problems, allocate one workspace on the current device (as
+ * laid out for swept_solve_batch), upload the table once and capture the
+ * reset and persistent kernels into a graph.  Synchronous; must not be
+ * called during stream capture.  opts may be NULL. */
 int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_opts *opts,
                     sw_batch *out);
 
@@ -275,9 +312,6 @@ int sw_batch_width(sw_batch batch, int problem);
 
 /* Synchronise the device and free everything the batch owns. */
 void sw_batch_destroy(sw_batch batch);
-
-/* create + run + wait + destroy. */
-int swept_solve_batch(int n_problems, const sw_problem *problems, sw_stream stream);
 
 /* Autotuner of the batched launch (the paper's advice to tune the block
  * width on a few steps before a long run, Sec. 6, applied to a batch).  The

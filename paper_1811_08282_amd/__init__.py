@@ -124,8 +124,15 @@ def load() -> ctypes.CDLL:
     lib.sw_batch_width.restype = i32
     lib.sw_batch_destroy.argtypes = [vp]
     lib.sw_batch_destroy.restype = None
-    lib.swept_solve_batch.argtypes = [i32, ctypes.POINTER(sw_problem), vp]
+    lib.swept_solve_batch.argtypes = [i32, ctypes.POINTER(sw_problem), vp, sz, vp]
     lib.swept_solve_batch.restype = i32
+    lib.swept_solve_batch_ex.argtypes = [i32, ctypes.POINTER(sw_problem),
+                                         ctypes.POINTER(sw_batch_opts), vp, sz, vp]
+    lib.swept_solve_batch_ex.restype = i32
+    lib.sw_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(sw_problem)]
+    lib.sw_batch_workspace_bytes.restype = sz
+    lib.sw_batch_check.argtypes = [vp, vp]
+    lib.sw_batch_check.restype = i32
     lib.sw_batch_item_deps.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i32)]
     lib.sw_batch_item_deps.restype = i32
     lib.sw_batch_autotune.argtypes = [i32, ctypes.POINTER(sw_problem), i64, vp,
@@ -319,9 +326,28 @@ def sw_batch_autotune(problems, probe_steps=0, stream=None, threads=0):
     return best.blocks_per_cu, best.threads, ms.value
 
 
-def swept_solve_batch(problems, stream=None) -> int:
+def sw_batch_workspace_bytes(problems) -> int:
+    """Device workspace bytes swept_solve_batch needs for ``problems`` (0 if invalid)."""
     arr = problem_array(problems)
-    return load().swept_solve_batch(len(arr), arr, stream)
+    return load().sw_batch_workspace_bytes(len(arr), arr)
+
+
+def swept_solve_batch(problems, d_ws, ws_bytes, stream=None, blocks_per_cu=0, threads=0,
+                      wait_limit_us=0) -> int:
+    """One persistent launch of ``problems`` in the caller's workspace ``d_ws``
+    (a device pointer of at least ``sw_batch_workspace_bytes(problems)``
+    bytes); asynchronous, allocates nothing.  Returns the status code."""
+    arr = problem_array(problems)
+    if blocks_per_cu or threads or wait_limit_us:
+        opts = sw_batch_opts(int(blocks_per_cu), int(threads), int(wait_limit_us))
+        return load().swept_solve_batch_ex(len(arr), arr, ctypes.byref(opts), d_ws, int(ws_bytes),
+                                           stream)
+    return load().swept_solve_batch(len(arr), arr, d_ws, int(ws_bytes), stream)
+
+
+def sw_batch_check(d_ws, stream=None) -> int:
+    """Wait for ``stream``; SW_ERR_HIP if the last launch in ``d_ws`` aborted."""
+    return load().sw_batch_check(d_ws, stream)
 
 
 # ---- torch convenience -----------------------------------------------------

@@ -1,4 +1,4 @@
-// batch.hip -- persistent kernel of the batched swept launch (tables and
+// batch.hip -- persistent kernel of the batched swept launch (table and
 // ordering described in batch.h).  One workgroup (256 or 512 threads) runs
 // one work item at a time with the same tile-phase bodies as the per-phase
 // kernels, so a problem solved in a batch is bit-identical to the same
@@ -24,20 +24,6 @@ __device__ __forceinline__ int load_acquire(const int *p)
 __device__ __forceinline__ void store_release(int *p, int v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// index of the segment holding item (segments sorted by start, first start 0)
-__device__ int64_t find_segment(const BatchSegment *seg, int64_t count, int64_t item)
-{
-    int64_t lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) / 2;
-        if (seg[mid].start <= item)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
 }
 
 // copy-out of a single-phase problem: level 1 sits in slot 1 of ws0
@@ -81,10 +67,10 @@ __global__ void __launch_bounds__(NT) k_batch_persistent(BatchTables b)
         const int64_t item = s_item;
         if (item >= b.n_items)
             return;  // uniform: every thread read the same s_item
-        const BatchSegment seg = b.segments[find_segment(b.segments, b.n_segments, item)];
-        const BatchProblem &P = b.problems[seg.problem];
-        const int k = seg.phase;
-        const int t = (int)(item - seg.start);
+        const BatchItem it = batch_item(b.problems, b.n_problems, item);
+        const BatchProblem &P = b.problems[it.problem];
+        const int k = it.phase;
+        const int t = it.tile;
 
         if (tid == 0) {
             int abort = 0;
@@ -183,6 +169,23 @@ __global__ void k_batch_reset(unsigned long long *ticket, int *status, int *flag
         flags[j] = 0;
 }
 
+// Table upload carried in the launch arguments: no host buffer has to outlive
+// the call, so the upload can be captured into a graph and replayed.
+constexpr int kPutWords = 256;  // 2 KiB of payload per launch
+
+struct PutChunk {
+    int64_t offset;  // destination byte offset, a multiple of 8
+    int64_t words;   // 8-byte words in this chunk, <= kPutWords
+    uint64_t data[kPutWords];
+};
+
+__global__ void k_batch_put(char *dst, PutChunk c)
+{
+    uint64_t *d = (uint64_t *)(dst + c.offset);
+    for (int64_t i = threadIdx.x; i < c.words; i += blockDim.x)
+        d[i] = c.data[i];
+}
+
 template <typename T>
 __global__ void k_fill(T *p, int64_t count, T v)
 {
@@ -232,6 +235,26 @@ void launch_persistent(int bodies, int blocks, size_t lds_bytes, hipStream_t s,
 
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s) { return fill(p, count, v, s); }
 hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s) { return fill(p, count, v, s); }
+
+hipError_t batch_put(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes % 8 != 0)
+        return hipErrorInvalidValue;
+    const uint64_t *w = (const uint64_t *)src;
+    const int64_t total = (int64_t)(bytes / 8);
+    for (int64_t at = 0; at < total; at += kPutWords) {
+        PutChunk c;
+        c.offset = at * 8;
+        c.words = total - at < kPutWords ? total - at : kPutWords;
+        for (int64_t i = 0; i < c.words; ++i)
+            c.data[i] = w[at + i];
+        hipLaunchKernelGGL(k_batch_put, dim3(1), dim3(256), 0, s, (char *)dst, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t batch_occupancy(size_t lds_bytes, int threads, int bodies, int *blocks_per_cu)
 {

@@ -9,9 +9,12 @@
 // when SWEPT_TUNE_CACHE names a file, persists the table there as text lines
 // "<arch> <eq> <n_cells> <width> <threads> <ms_per_cell_update>".
 //
-// Batch: sw_batch_create builds the work-item tables (batch.h), allocates the
-// working arrays of every problem and captures the reset kernel and the
-// persistent kernel into a hipGraph; sw_batch_run launches that graph.
+// Batch: a problem list is planned on the host into one table (batch.h,
+// batch_plan.h) and a workspace layout (header, table, tile flags, working
+// arrays).  swept_solve_batch enqueues the table upload, the reset kernel and
+// the persistent kernel into a caller-owned workspace; sw_batch_create
+// allocates the workspace itself, uploads the table once and captures the
+// reset and persistent kernels into a hipGraph that sw_batch_run launches.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -22,12 +25,14 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <tuple>
 #include <vector>
 
 #include "../../include/swept.h"
 #include "batch.h"
+#include "batch_plan.h"
 #include "geom.h"
 #include "host.h"
 #include "kernels.h"
@@ -38,6 +43,10 @@ namespace sw {
 hipError_t batch_occupancy(size_t lds_bytes, int threads, int bodies, int *blocks_per_cu);
 hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, int threads,
                         int bodies, size_t lds_bytes, hipStream_t s);
+// copy `bytes` (a multiple of 8) from host memory to device memory `dst` by
+// kernels that carry the data in their arguments (capturable, no host buffer
+// has to outlive the call)
+hipError_t batch_put(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s);
 hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s);
 
@@ -207,22 +216,198 @@ hipError_t fill_state(int eq, void *state, int64_t n, hipStream_t s)
 
 using namespace sw::host;
 
+// ---- batch planning and launch ---------------------------------------------
+
+namespace {
+
+constexpr size_t kHeaderBytes = 256;  // ticket (8 B at 0) and status word (4 B at 8)
+constexpr int64_t kMaxBatchPhase = (int64_t)INT32_MAX - 1;
+
+// Byte layout of a batch workspace: header, sorted problem table, tile
+// flags, every problem's two working arrays.  All parts are 256-byte aligned.
+struct PreparedBatch {
+    sw::BatchPlan plan;
+    std::vector<int> widths;        // caller order
+    std::vector<size_t> array_off;  // caller order, within the array part
+    size_t array_bytes = 0;
+    size_t max_lds = 0;
+    int bodies = 0;                 // 0 every tile body, 1 heat binary64 only, 2 heat binary32 only
+    size_t off_table = 0, off_flags = 0, off_arrays = 0, total = 0;
+};
+
+int check_batch_opts(const sw_batch_opts *opts)
+{
+    if (opts && (opts->blocks_per_cu < 0 || opts->wait_limit_us < 0))
+        return fail(SW_ERR_ARG, "invalid batch options");
+    if (opts && opts->threads != 0 && opts->threads != 256 && opts->threads != 512)
+        return fail(SW_ERR_ARG, "batch threads must be 0, 256 or 512");
+    return SW_OK;
+}
+
+// Validate the problems and plan the batch (host only; no HIP call unless a
+// tuned width has been recorded, whose lookup asks for the current device).
+int prepare_batch(int n_problems, const sw_problem *problems, PreparedBatch *pb)
+{
+    if (n_problems < 1 || !problems)
+        return fail(SW_ERR_ARG, "empty problem list");
+    std::vector<sw::BatchProblem> in(n_problems);
+    pb->widths.assign(n_problems, 0);
+    pb->array_off.assign(n_problems, 0);
+    size_t arrays = 0;
+    bool all64 = true, all32 = true;
+    for (int i = 0; i < n_problems; ++i) {
+        const sw_problem &p = problems[i];
+        int rc = check_common(p.eq, p.n_cells, p.n_steps, p.dt, p.dx, p.d_state, 4);
+        if (rc)
+            return fail(rc, "problem %d: %s", i, last_error());
+        if (p.width && !width_ok(p.eq, p.n_cells, p.width))
+            return fail(SW_ERR_ARG, "problem %d: width %d invalid for n_cells %lld", i, p.width,
+                        (long long)p.n_cells);
+        const int w = p.width ? p.width : chosen_width(-1, p.eq, p.n_cells, nullptr, true);
+        if (!w)
+            return fail(SW_ERR_UNSUPPORTED, "problem %d: no valid width for n_cells %lld", i,
+                        (long long)p.n_cells);
+        if (p.n_cells / w > (int64_t)INT32_MAX)
+            return fail(SW_ERR_ARG, "problem %d: %lld tiles of %d cells exceed 2^31 - 1", i,
+                        (long long)(p.n_cells / w), w);
+        sw::BatchProblem &b = in[i];
+        b = sw::BatchProblem{};
+        b.state = p.d_state;
+        b.n = p.n_cells;
+        b.w = w;
+        b.eq = p.eq;
+        b.tiles = (int)(p.n_cells / w);
+        b.final_level = p.n_steps * substeps(p.eq);
+        b.radius = radius(p.eq);
+        b.phases = sw::phase_count(b.final_level, w / (2 * b.radius));
+        b.single_phase = (b.phases == 1);
+        if (b.phases + b.single_phase > kMaxBatchPhase)
+            return fail(SW_ERR_ARG, "problem %d: %lld phases exceed 2^31 - 2 (use a wider tile)",
+                        i, (long long)b.phases);
+        b.item_phases = (int)(b.phases + b.single_phase);
+        b.coef = is_euler(p.eq) ? p.dt / p.dx : p.dt / (p.dx * p.dx);
+        if (is_f32(p.eq))
+            b.coef = (double)(float)b.coef;
+        pb->widths[i] = w;
+        pb->array_off[i] = arrays;
+        arrays += 2 * swept_copy_bytes(p.eq, p.n_cells);
+        pb->max_lds = std::max(pb->max_lds, (size_t)(w + 2 * b.radius) * (size_t)lds_per_cell(p.eq));
+        all64 = all64 && p.eq == SW_HEAT_F64;
+        all32 = all32 && p.eq == SW_HEAT_F32;
+    }
+    if (!sw::plan_batch(in, &pb->plan))
+        return fail(SW_ERR_ARG, "the batch has more than 2^63 work items");
+    // a batch of heat problems of one precision runs the kernel compiled with
+    // that body alone (fewer registers, more resident workgroups)
+    pb->bodies = all64 ? 1 : (all32 ? 2 : 0);
+    pb->array_bytes = arrays;
+    pb->off_table = kHeaderBytes;
+    pb->off_flags = pb->off_table + round_up(sizeof(sw::BatchProblem) * (size_t)n_problems, 256);
+    pb->off_arrays = pb->off_flags + round_up(sizeof(int) * (size_t)pb->plan.n_flags, 256);
+    pb->total = pb->off_arrays + arrays;
+    return SW_OK;
+}
+
+// Every problem's state on the current device (HIP queries, no allocation).
+int check_batch_pointers(int n_problems, const sw_problem *problems, int *dev)
+{
+    for (int i = 0; i < n_problems; ++i) {
+        int d = 0;
+        int rc = check_device_pointer(problems[i].d_state, &d);
+        if (rc)
+            return fail(rc, "problem %d: %s", i, last_error());
+        *dev = d;
+    }
+    return SW_OK;
+}
+
+// Working-array pointers of the table entries inside workspace `ws`.
+void place_arrays(PreparedBatch *pb, char *ws)
+{
+    for (size_t s = 0; s < pb->plan.table.size(); ++s) {
+        sw::BatchProblem &b = pb->plan.table[s];
+        const int i = pb->plan.order[s];
+        const size_t copy = swept_copy_bytes(b.eq, b.n);
+        b.ws0 = ws + pb->off_arrays + pb->array_off[i];
+        b.ws1 = (char *)b.ws0 + copy;
+    }
+}
+
+sw::BatchTables device_tables(const PreparedBatch &pb, char *ws, const sw_batch_opts *opts)
+{
+    sw::BatchTables t;
+    t.problems = (const sw::BatchProblem *)(ws + pb.off_table);
+    t.n_problems = (int)pb.plan.table.size();
+    t.n_items = pb.plan.n_items;
+    t.ticket = (unsigned long long *)ws;
+    t.status = (int *)(ws + 8);
+    t.flags = (int *)(ws + pb.off_flags);
+    const long long limit_us = (opts && opts->wait_limit_us) ? opts->wait_limit_us : 10000000LL;
+    t.wait_limit = limit_us * 100;  // s_memrealtime runs at 100 MHz
+    return t;
+}
+
+// Resident workgroups of the persistent launch: CUs x occupancy (capped by
+// opts->blocks_per_cu), at most one per item.
+int batch_blocks(const PreparedBatch &pb, int dev, int threads, const sw_batch_opts *opts,
+                 int *blocks)
+{
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        sw::batch_occupancy(pb.max_lds, threads, pb.bodies, &per_cu) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_HIP, "batch occupancy query failed (LDS %zu bytes)", pb.max_lds);
+    }
+    if (opts && opts->blocks_per_cu)
+        per_cu = std::min(per_cu, opts->blocks_per_cu);
+    int64_t b = (int64_t)cus * per_cu;
+    if (b > pb.plan.n_items)
+        b = std::max<int64_t>(pb.plan.n_items, 1);
+    *blocks = (int)b;
+    return SW_OK;
+}
+
+// Table upload: kernels that carry the table in their launch arguments, so
+// no host buffer outlives the call and the upload can be captured.
+int upload_table(const PreparedBatch &pb, char *ws, hipStream_t s)
+{
+    return launched(sw::batch_put(ws + pb.off_table, pb.plan.table.data(),
+                                  sizeof(sw::BatchProblem) * pb.plan.table.size(), s),
+                    "batch table upload");
+}
+
+// The reset kernel and the persistent kernel on `s`: nothing is allocated,
+// nothing waits, and the pair can be captured into a graph.
+int launch_run(const PreparedBatch &pb, char *ws, const sw_batch_opts *opts, int blocks,
+               int threads, hipStream_t s)
+{
+    const sw::BatchTables t = device_tables(pb, ws, opts);
+    return launched(sw::batch_launch(t, pb.plan.n_flags, blocks, threads, pb.bodies, pb.max_lds, s),
+                    "batch launch");
+}
+
+template <typename F>
+int guarded(F f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return fail(SW_ERR_NOMEM, "host memory exhausted");
+    }
+}
+
+} // namespace
+
 // ---- batch handle -------------------------------------------------------------
 
 struct sw_batch_impl {
     int device = 0;
-    void *tables = nullptr;      // problems, segments, ticket, status, flags
-    void *arrays = nullptr;      // every problem's working arrays
-    size_t array_bytes = 0;
-    size_t table_bytes = 0;
+    char *ws = nullptr;          // header, table, flags, working arrays
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int *d_status = nullptr;
     int64_t items = 0;
-    int64_t flags = 0;
     int blocks = 0;
-    int threads = 256;
-    int bodies = 0;
+    size_t array_bytes = 0;
     std::vector<int> widths;
 };
 
@@ -236,20 +421,126 @@ void free_batch(sw_batch_impl *b)
         (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
-    if (b->tables)
-        (void)hipFree(b->tables);
-    if (b->arrays)
-        (void)hipFree(b->arrays);
+    if (b->ws)
+        (void)hipFree(b->ws);
     (void)hipGetLastError();
     delete b;
+}
+
+int batch_create(int n_problems, const sw_problem *problems, const sw_batch_opts *opts,
+                 sw_batch *out)
+{
+    if (!out)
+        return fail(SW_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_batch_opts(opts);
+    if (rc)
+        return rc;
+    const int threads = (opts && opts->threads) ? opts->threads : 256;
+    PreparedBatch pb;
+    rc = prepare_batch(n_problems, problems, &pb);
+    if (rc)
+        return rc;
+    int dev = 0;
+    rc = check_batch_pointers(n_problems, problems, &dev);
+    if (rc)
+        return rc;
+    int blocks = 0;
+    rc = batch_blocks(pb, dev, threads, opts, &blocks);
+    if (rc)
+        return rc;
+
+    sw_batch_impl *b = new sw_batch_impl();
+    b->device = dev;
+    b->widths = pb.widths;
+    b->items = pb.plan.n_items;
+    b->blocks = blocks;
+    b->array_bytes = pb.array_bytes;
+    if (hipMalloc(&b->ws, pb.total) != hipSuccess) {
+        (void)hipGetLastError();
+        b->ws = nullptr;
+        free_batch(b);
+        return fail(SW_ERR_NOMEM, "batch allocation of %zu bytes failed", pb.total);
+    }
+    place_arrays(&pb, b->ws);
+    // the table is uploaded once; the ticket and the status word start at
+    // zero so that sw_batch_wait before any run reports success (each run
+    // resets them on the device).  Then the reset and persistent kernels are
+    // captured into a graph on the same private stream.
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(b->ws, 0, kHeaderBytes, cap);
+    if (e == hipSuccess && upload_table(pb, b->ws, cap) != SW_OK)
+        e = hipErrorLaunchFailure;
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(cap);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = launch_run(pb, b->ws, opts, blocks, threads, cap);
+        e = hipStreamEndCapture(cap, &b->graph);
+        if (rc != SW_OK && e == hipSuccess)
+            e = hipErrorLaunchFailure;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiateWithFlags(&b->exec, b->graph, 0);
+    if (cap)
+        (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_batch(b);
+        return fail(SW_ERR_HIP, "building the batch graph failed: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return ok();
+}
+
+int batch_solve(int n_problems, const sw_problem *problems, const sw_batch_opts *opts,
+                void *d_ws, size_t ws_bytes, hipStream_t s)
+{
+    int rc = check_batch_opts(opts);
+    if (rc)
+        return rc;
+    const int threads = (opts && opts->threads) ? opts->threads : 256;
+    PreparedBatch pb;
+    rc = prepare_batch(n_problems, problems, &pb);
+    if (rc)
+        return rc;
+    if (!d_ws)
+        return fail(SW_ERR_ARG, "d_ws is NULL (size it with sw_batch_workspace_bytes)");
+    if (((uintptr_t)d_ws & 255) != 0)
+        return fail(SW_ERR_ARG, "d_ws must be 256-byte aligned");
+    if (ws_bytes < pb.total)
+        return fail(SW_ERR_ARG, "workspace of %zu bytes is smaller than the %zu the batch needs",
+                    ws_bytes, pb.total);
+    if (pb.plan.n_items == 0)
+        return ok();
+    int dev = 0;
+    rc = check_batch_pointers(n_problems, problems, &dev);
+    if (rc)
+        return rc;
+    int wdev = 0;
+    rc = check_device_pointer(d_ws, &wdev);
+    if (rc)
+        return fail(rc, "d_ws: %s", last_error());
+    int blocks = 0;
+    rc = batch_blocks(pb, dev, threads, opts, &blocks);
+    if (rc)
+        return rc;
+    place_arrays(&pb, (char *)d_ws);
+    rc = upload_table(pb, (char *)d_ws, s);
+    if (rc == SW_OK)
+        rc = launch_run(pb, (char *)d_ws, opts, blocks, threads, s);
+    return rc ? rc : ok();
 }
 
 } // namespace
 
 extern "C" {
 
-int sw_autotune(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream, sw_opts *best,
-                double *best_ms_per_update)
+static int autotune_impl(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream,
+                         sw_opts *best, double *best_ms_per_update)
 {
     if (!valid_eq(eq))
         return fail(SW_ERR_ARG, "invalid equation id %d", eq);
@@ -351,6 +642,13 @@ int sw_autotune(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream, 
     return ok();
 }
 
+int sw_autotune(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream, sw_opts *best,
+                double *best_ms_per_update)
+{
+    return guarded(
+        [&] { return autotune_impl(eq, n_cells, probe_steps, stream, best, best_ms_per_update); });
+}
+
 int sw_tuned_width(int eq, int64_t n_cells, int *width, int *threads)
 {
     if (!valid_eq(eq) || !width)
@@ -382,182 +680,7 @@ void sw_tune_clear(void)
 int sw_batch_create(int n_problems, const sw_problem *problems, const sw_batch_opts *opts,
                     sw_batch *out)
 {
-    if (!out)
-        return fail(SW_ERR_ARG, "out is NULL");
-    *out = nullptr;
-    if (n_problems < 1 || !problems)
-        return fail(SW_ERR_ARG, "empty problem list");
-    if (opts && (opts->blocks_per_cu < 0 || opts->wait_limit_us < 0))
-        return fail(SW_ERR_ARG, "invalid batch options");
-    if (opts && opts->threads != 0 && opts->threads != 256 && opts->threads != 512)
-        return fail(SW_ERR_ARG, "batch threads must be 0, 256 or 512");
-    const int threads = (opts && opts->threads) ? opts->threads : 256;
-    for (int i = 0; i < n_problems; ++i) {
-        const sw_problem &p = problems[i];
-        int rc = check_common(p.eq, p.n_cells, p.n_steps, p.dt, p.dx, p.d_state, 4);
-        if (rc)
-            return fail(rc, "problem %d: %s", i, last_error());
-        if (p.width && !width_ok(p.eq, p.n_cells, p.width))
-            return fail(SW_ERR_ARG, "problem %d: width %d invalid for n_cells %lld", i, p.width,
-                        (long long)p.n_cells);
-    }
-    int dev = 0;
-    int rc = check_device_pointer(problems[0].d_state, &dev);
-    if (rc)
-        return rc;
-    for (int i = 1; i < n_problems; ++i) {
-        int d = 0;
-        rc = check_device_pointer(problems[i].d_state, &d);
-        if (rc)
-            return fail(rc, "problem %d: %s", i, last_error());
-    }
-
-    std::vector<sw::BatchProblem> hp(n_problems);
-    std::vector<int> widths(n_problems);
-    size_t array_bytes = 0, max_lds = 0;
-    int64_t flags = 0;
-    int64_t max_phase = 0;
-    for (int i = 0; i < n_problems; ++i) {
-        const sw_problem &p = problems[i];
-        int w = p.width;
-        if (!w) {
-            w = chosen_width(dev, p.eq, p.n_cells, nullptr, true);
-            if (!w)
-                return fail(SW_ERR_UNSUPPORTED, "problem %d: no valid width for n_cells %lld", i,
-                            (long long)p.n_cells);
-        }
-        if (p.n_cells / w > (int64_t)INT32_MAX)
-            return fail(SW_ERR_ARG, "problem %d: %lld tiles of %d cells exceed 2^31 - 1", i,
-                        (long long)(p.n_cells / w), w);
-        widths[i] = w;
-        sw::BatchProblem &b = hp[i];
-        b.state = p.d_state;
-        b.n = p.n_cells;
-        b.w = w;
-        b.eq = p.eq;
-        b.tiles = (int)(p.n_cells / w);
-        b.final_level = p.n_steps * substeps(p.eq);
-        b.radius = radius(p.eq);
-        b.phases = sw::phase_count(b.final_level, w / (2 * b.radius));
-        b.single_phase = (b.phases == 1);
-        b.coef = is_euler(p.eq) ? p.dt / p.dx : p.dt / (p.dx * p.dx);
-        if (is_f32(p.eq))
-            b.coef = (double)(float)b.coef;
-        b.flag_off = flags;
-        flags += b.tiles;
-        array_bytes += 2 * swept_copy_bytes(p.eq, p.n_cells);
-        max_lds = std::max(max_lds, (size_t)(w + 2 * b.radius) * (size_t)lds_per_cell(p.eq));
-        max_phase = std::max<int64_t>(max_phase, b.phases + (b.single_phase ? 1 : 0));
-    }
-    // segments, phase-major
-    std::vector<sw::BatchSegment> segs;
-    int64_t items = 0;
-    for (int64_t k = 1; k <= max_phase; ++k)
-        for (int i = 0; i < n_problems; ++i) {
-            const int64_t pk = hp[i].phases + (hp[i].single_phase ? 1 : 0);
-            if (k > pk)
-                continue;
-            segs.push_back(sw::BatchSegment{items, i, (int)k});
-            items += hp[i].tiles;
-        }
-
-    sw_batch_impl *b = new sw_batch_impl();
-    // a batch of heat problems of one precision runs the kernel compiled with
-    // that body alone (fewer registers, more resident workgroups)
-    int bodies = 0;
-    {
-        bool all64 = true, all32 = true;
-        for (int i = 0; i < n_problems; ++i) {
-            all64 = all64 && problems[i].eq == SW_HEAT_F64;
-            all32 = all32 && problems[i].eq == SW_HEAT_F32;
-        }
-        bodies = all64 ? 1 : (all32 ? 2 : 0);
-    }
-    b->device = dev;
-    b->threads = threads;
-    b->bodies = bodies;
-    b->widths = widths;
-    b->items = items;
-    b->flags = flags;
-    const size_t off_seg = round_up(sizeof(sw::BatchProblem) * n_problems, 256);
-    const size_t off_ticket = off_seg + round_up(sizeof(sw::BatchSegment) * std::max<size_t>(segs.size(), 1), 256);
-    const size_t off_status = off_ticket + 256;
-    const size_t off_flags = off_status + 256;
-    b->table_bytes = off_flags + round_up(sizeof(int) * std::max<int64_t>(flags, 1), 256);
-    b->array_bytes = array_bytes;
-    if (hipMalloc(&b->tables, b->table_bytes) != hipSuccess ||
-        (array_bytes && hipMalloc(&b->arrays, array_bytes) != hipSuccess)) {
-        const size_t table_bytes = b->table_bytes;
-        free_batch(b);
-        return fail(SW_ERR_NOMEM, "batch allocation of %zu + %zu bytes failed", table_bytes,
-                    array_bytes);
-    }
-    char *arr = (char *)b->arrays;
-    for (int i = 0; i < n_problems; ++i) {
-        const size_t copy = swept_copy_bytes(hp[i].eq, hp[i].n);
-        hp[i].ws0 = arr;
-        hp[i].ws1 = arr + copy;
-        arr += 2 * copy;
-    }
-    char *tb = (char *)b->tables;
-    // the ticket and the status word start at zero, so that sw_batch_wait
-    // before any run reports success (each run resets them on the device)
-    if (hipMemcpy(tb, hp.data(), sizeof(sw::BatchProblem) * n_problems, hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        (!segs.empty() && hipMemcpy(tb + off_seg, segs.data(), sizeof(sw::BatchSegment) * segs.size(),
-                                    hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemset(tb + off_ticket, 0, off_flags - off_ticket) != hipSuccess) {
-        free_batch(b);
-        return fail(SW_ERR_HIP, "uploading batch tables failed");
-    }
-    sw::BatchTables t;
-    t.problems = (const sw::BatchProblem *)tb;
-    t.segments = (const sw::BatchSegment *)(tb + off_seg);
-    t.n_segments = (int64_t)segs.size();
-    t.n_items = items;
-    t.ticket = (unsigned long long *)(tb + off_ticket);
-    t.status = (int *)(tb + off_status);
-    t.flags = (int *)(tb + off_flags);
-    const long long limit_us = (opts && opts->wait_limit_us) ? opts->wait_limit_us : 10000000LL;
-    t.wait_limit = limit_us * 100;  // s_memrealtime runs at 100 MHz
-    b->d_status = t.status;
-
-    int cus = 0, per_cu = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        sw::batch_occupancy(max_lds, threads, bodies, &per_cu) != hipSuccess || per_cu < 1) {
-        (void)hipGetLastError();
-        free_batch(b);
-        return fail(SW_ERR_HIP, "batch occupancy query failed (LDS %zu bytes)", max_lds);
-    }
-    if (opts && opts->blocks_per_cu)
-        per_cu = std::min(per_cu, opts->blocks_per_cu);
-    int64_t blocks = (int64_t)cus * per_cu;
-    if (blocks > items)
-        blocks = std::max<int64_t>(items, 1);
-    b->blocks = (int)blocks;
-
-    // capture reset + persistent kernel into a graph on a private stream
-    hipStream_t cap = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e == hipSuccess)
-        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipError_t le = sw::batch_launch(t, flags, b->blocks, threads, bodies, max_lds, cap);
-        e = hipStreamEndCapture(cap, &b->graph);
-        if (le != hipSuccess)
-            e = le;
-    }
-    if (e == hipSuccess)
-        e = hipGraphInstantiateWithFlags(&b->exec, b->graph, 0);
-    if (cap)
-        (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        free_batch(b);
-        return fail(SW_ERR_HIP, "building the batch graph failed: %s", hipGetErrorString(e));
-    }
-    *out = b;
-    return ok();
+    return guarded([&] { return batch_create(n_problems, problems, opts, out); });
 }
 
 int sw_batch_run(sw_batch b, sw_stream stream)
@@ -574,11 +697,17 @@ int sw_batch_wait(sw_batch b, sw_stream stream)
 {
     if (!b)
         return fail(SW_ERR_ARG, "batch is NULL");
-    hipStream_t s = (hipStream_t)stream;
+    return sw_batch_check(b->ws, stream);
+}
+
+int sw_batch_check(const void *d_ws, sw_stream stream)
+{
+    if (!d_ws)
+        return fail(SW_ERR_ARG, "d_ws is NULL");
     int status = 0;
-    hipError_t e = hipStreamSynchronize(s);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e == hipSuccess)
-        e = hipMemcpy(&status, b->d_status, sizeof(int), hipMemcpyDeviceToHost);
+        e = hipMemcpy(&status, (const char *)d_ws + 8, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return launched(e, "waiting for the batch");
     if (status)
@@ -621,22 +750,37 @@ int sw_batch_item_deps(int phase, int tile, int tiles, int single_phase, int *de
     return sw::batch_deps(phase, tile, tiles, single_phase, deps);
 }
 
-int swept_solve_batch(int n_problems, const sw_problem *problems, sw_stream stream)
+size_t sw_batch_workspace_bytes(int n_problems, const sw_problem *problems)
 {
-    sw_batch b = nullptr;
-    int rc = sw_batch_create(n_problems, problems, nullptr, &b);
-    if (rc)
-        return rc;
-    rc = sw_batch_run(b, stream);
-    if (rc == SW_OK)
-        rc = sw_batch_wait(b, stream);
-    const std::string msg = last_error();
-    sw_batch_destroy(b);
-    return rc ? fail(rc, "%s", msg.c_str()) : ok();
+    size_t total = 0;
+    const int rc = guarded([&] {
+        PreparedBatch pb;
+        const int r = prepare_batch(n_problems, problems, &pb);
+        if (r == SW_OK)
+            total = pb.total;
+        return r;
+    });
+    return rc == SW_OK ? total : 0;
 }
 
-int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
-                      sw_stream stream, sw_batch_opts *best, double *best_ms_per_update)
+int swept_solve_batch(int n_problems, const sw_problem *problems, void *d_ws, size_t ws_bytes,
+                      sw_stream stream)
+{
+    return guarded([&] {
+        return batch_solve(n_problems, problems, nullptr, d_ws, ws_bytes, (hipStream_t)stream);
+    });
+}
+
+int swept_solve_batch_ex(int n_problems, const sw_problem *problems, const sw_batch_opts *opts,
+                         void *d_ws, size_t ws_bytes, sw_stream stream)
+{
+    return guarded([&] {
+        return batch_solve(n_problems, problems, opts, d_ws, ws_bytes, (hipStream_t)stream);
+    });
+}
+
+static int batch_autotune_impl(int n_problems, sw_problem *problems, int64_t probe_steps,
+                               sw_stream stream, sw_batch_opts *best, double *best_ms_per_update)
 {
     if (!best)
         return fail(SW_ERR_ARG, "best is NULL");
@@ -846,6 +990,15 @@ int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
     if (best_ms_per_update)
         *best_ms_per_update = work > 0.0 ? best_ms / work : 0.0;
     return ok();
+}
+
+int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
+                      sw_stream stream, sw_batch_opts *best, double *best_ms_per_update)
+{
+    return guarded([&] {
+        return batch_autotune_impl(n_problems, problems, probe_steps, stream, best,
+                                   best_ms_per_update);
+    });
 }
 
 } // extern "C"

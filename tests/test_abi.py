@@ -164,3 +164,60 @@ def test_workgroup_sizes_checked_on_host():
     for threads in (64, 128, 256, 512):  # accepted (zero steps: no device call)
         assert sw.swept_solve_ex(sw.EULER_F64, 4096, 0, 0.1, 1.0, FAKE, None, width=1024,
                                  threads=threads) == sw.SW_OK
+
+
+def _ru(x, a=256):
+    return (x + a - 1) // a * a
+
+
+def test_batch_workspace_bytes_layout():
+    """Header, problem table (96 bytes per entry), one 32-bit flag per tile,
+    then both working-array copies of every problem, each part 256-aligned."""
+    probs = [dict(eq=sw.HEAT_F64, width=64, n_cells=1024, n_steps=100, dt=0.25, dx=1.0,
+                  d_state=FAKE),
+             dict(eq=sw.EULER_F32, width=128, n_cells=3 * 1024, n_steps=7, dt=0.1, dx=1.0,
+                  d_state=FAKE + 4096),
+             dict(eq=sw.EULER_F64_FLAT, width=256, n_cells=1024, n_steps=1, dt=0.1, dx=1.0,
+                  d_state=FAKE + 8192)]
+    tiles = 1024 // 64 + 3 * 1024 // 128 + 1024 // 256
+    arrays = 2 * _ru(1024 * 16) + 2 * _ru(3 * 1024 * 44) + 2 * _ru(1024 * 48)
+    want = 256 + _ru(3 * 96) + _ru(4 * tiles) + arrays
+    assert sw.sw_batch_workspace_bytes(probs) == want
+    # the same list with one problem more changes every part
+    more = probs + [dict(probs[0], d_state=FAKE + 12288)]
+    assert sw.sw_batch_workspace_bytes(more) == (256 + _ru(4 * 96) + _ru(4 * (tiles + 16))
+                                                 + arrays + 2 * _ru(1024 * 16))
+
+
+def test_batch_workspace_checked_on_host():
+    """swept_solve_batch rejects a missing, misaligned or short workspace and
+    an invalid list before any HIP call (this runs without a GPU)."""
+    probs = [dict(eq=sw.HEAT_F64, width=64, n_cells=1024, n_steps=100, dt=0.25, dx=1.0,
+                  d_state=FAKE)]
+    need = sw.sw_batch_workspace_bytes(probs)
+    assert need > 0
+    assert sw.swept_solve_batch(probs, None, need) == sw.SW_ERR_ARG
+    assert "d_ws" in sw.last_error()
+    assert sw.swept_solve_batch(probs, FAKE + 128, need) == sw.SW_ERR_ARG
+    assert "aligned" in sw.last_error()
+    assert sw.swept_solve_batch(probs, FAKE, need - 1) == sw.SW_ERR_ARG
+    assert "smaller" in sw.last_error()
+    assert sw.swept_solve_batch(probs, FAKE, need, threads=384) == sw.SW_ERR_ARG
+    bad = [dict(probs[0], width=48)]  # does not divide 1024
+    assert sw.sw_batch_workspace_bytes(bad) == 0
+    assert sw.swept_solve_batch(bad, FAKE, need) == sw.SW_ERR_ARG
+    # zero steps everywhere: nothing to launch, no device call
+    idle = [dict(probs[0], n_steps=0)]
+    assert sw.swept_solve_batch(idle, FAKE, sw.sw_batch_workspace_bytes(idle)) == sw.SW_OK
+
+
+def test_batch_phase_count_bounded_on_host():
+    """More than 2^31 - 2 swept phases cannot be numbered by the 32-bit tile
+    flags: rejected on the host instead of truncated."""
+    probs = [dict(eq=sw.HEAT_F64, width=4, n_cells=1024, n_steps=1 << 33, dt=0.25, dx=1.0,
+                  d_state=FAKE)]
+    assert sw.sw_batch_workspace_bytes(probs) == 0
+    assert "phases" in sw.last_error()
+    h = ctypes.c_void_p()
+    arr = sw.problem_array(probs)
+    assert sw.load().sw_batch_create(1, arr, None, ctypes.byref(h)) == sw.SW_ERR_ARG

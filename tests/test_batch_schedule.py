@@ -146,3 +146,20 @@ def test_emulator_catches_a_weaker_rule(monkeypatch):
                 caught += 1
         assert caught >= 5
     monkeypatch.setattr(sw, "sw_batch_item_deps", orig)
+
+
+def test_item_numbering_is_a_phase_major_bijection(tmp_path):
+    """The persistent kernel resolves a ticket number through the sorted
+    problem table alone (two binary searches, no per-phase table).  A host
+    build of that lookup and of the planner, over 300 random problem lists,
+    must map the item numbers one to one onto (problem, phase, tile) with
+    phases non-decreasing."""
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    csrc = os.path.join(os.path.dirname(here), "paper_1811_08282_amd", "csrc")
+    exe = str(tmp_path / "batch_table_check")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-Wall", "-I", csrc, "-o", exe,
+                    os.path.join(here, "batch_table_check.cpp")], check=True)
+    out = subprocess.run([exe, "300"], check=True, capture_output=True, text=True)
+    assert out.stdout.startswith("ok 300")

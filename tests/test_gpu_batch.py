@@ -119,16 +119,72 @@ def test_graph_replays_match_eager_runs():
     b.close()
 
 
-def test_default_widths_and_one_shot_entry_point():
+def _batch_ws(probs):
     import torch
-    specs = [(sw.HEAT_F64, 256 * 5, 50, 0, 21), (sw.EULER_F32, 256 * 6, 20, 0, 22)]
+    nbytes = sw.sw_batch_workspace_bytes(probs)
+    assert nbytes > 0, sw.last_error()
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    assert ws.data_ptr() % 256 == 0
+    return ws, nbytes
+
+
+def test_default_widths_and_one_shot_entry_point():
+    """swept_solve_batch in a caller workspace, library-chosen widths: every
+    problem equals its own swept solve; a second call with a smaller list
+    reuses the same workspace."""
+    import torch
+    specs = [(sw.HEAT_F64, 256 * 5, 50, 0, 21), (sw.EULER_F32, 256 * 6, 20, 0, 22),
+             (sw.EULER_F64_FLAT, 256 * 4, 33, 0, 23)]
     tensors, hosts, probs = _problems(specs)
-    announce("batch one-shot")
-    assert sw.swept_solve_batch(probs, torch.cuda.current_stream().cuda_stream) == sw.SW_OK
+    ws, nbytes = _batch_ws(probs)
+    stream = torch.cuda.current_stream().cuda_stream
+    announce("batch one-shot", len(probs))
+    assert sw.swept_solve_batch(probs, ws.data_ptr(), nbytes, stream) == sw.SW_OK, sw.last_error()
+    assert sw.sw_batch_check(ws.data_ptr(), stream) == sw.SW_OK
     for (eq, n, steps, width, seed), t, host in zip(specs, tensors, hosts):
         dt, dx = _coef(eq)
-        alone = run(eq, host, steps, dt, dx, "swept")  # the same default width
+        alone = run(eq, host, steps, dt, dx, "swept")
         assert np.array_equal(t.cpu().numpy(), alone)
+    small = [(sw.HEAT_F32, 512, 70, 0, 24)]
+    tensors, hosts, probs = _problems(small)
+    announce("batch one-shot, smaller list in the same workspace")
+    assert sw.swept_solve_batch(probs, ws.data_ptr(), nbytes, stream) == sw.SW_OK, sw.last_error()
+    assert sw.sw_batch_check(ws.data_ptr(), stream) == sw.SW_OK
+    alone = run(sw.HEAT_F32, hosts[0], 70, 0.25, 1.0, "swept")
+    assert np.array_equal(tensors[0].cpu().numpy(), alone)
+
+
+@pytest.mark.parametrize("threads", [0, 512])
+def test_swept_solve_batch_captured_in_a_graph(threads):
+    """swept_solve_batch captured into a HIP graph (table upload, reset and
+    persistent kernels): the capture runs nothing, and each of three replays,
+    with eager solves and host synchronisation between them, equals the same
+    number of eager solves of every problem."""
+    import torch
+    specs = [(sw.HEAT_F64, 2048, 97, 128, 81), (sw.EULER_F64, 1024, 13, 64, 82),
+             (sw.HEAT_F32, 1024, 1, 64, 83), (sw.EULER_F32_FLAT, 2048, 9, 256, 84)]
+    tensors, hosts, probs = _problems(specs)
+    ws, nbytes = _batch_ws(probs)
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    announce("batch graph capture", threads)
+    with torch.cuda.graph(graph, stream=stream):
+        rc = sw.swept_solve_batch(probs, ws.data_ptr(), nbytes,
+                                  torch.cuda.current_stream().cuda_stream, threads=threads)
+    assert rc == sw.SW_OK, sw.last_error()
+    torch.cuda.synchronize()
+    for t, h in zip(tensors, hosts):
+        assert np.array_equal(t.cpu().numpy(), h)  # capture runs nothing
+    eager = [h.copy() for h in hosts]
+    for rep in range(3):
+        announce("batch graph replay", rep)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert sw.sw_batch_check(ws.data_ptr(), None) == sw.SW_OK
+        for i, (eq, n, steps, width, seed) in enumerate(specs):
+            dt, dx = _coef(eq)
+            eager[i] = run(eq, eager[i], steps, dt, dx, "swept", width=width)
+            assert np.array_equal(tensors[i].cpu().numpy(), eager[i]), (rep, i)
 
 
 def test_bounded_wait_aborts_cleanly():
