@@ -56,6 +56,57 @@ def test_heat_f64_n4194304_20000_steps():
         assert np.array_equal(got, vals), s
 
 
+def _persistent_solve(eq, host, work, threads=256):
+    """One persistent launch of the heat-only batch holding the single
+    problem, the launch bench.py times for heat grids (library width for a
+    batch, 256-thread workgroups)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(host)).cuda()
+    torch.cuda.synchronize()
+    b = sw.Batch([dict(eq=eq, width=0, n_cells=work.n, n_steps=work.steps, dt=work.dt,
+                       dx=work.dx, d_state=t.data_ptr())], threads=threads)
+    stream = torch.cuda.current_stream().cuda_stream
+    b.run(stream)
+    assert b.wait(stream) == sw.SW_OK, sw.last_error()
+    width = b.width(0)
+    b.close()
+    return t.cpu().numpy(), width
+
+
+@pytest.mark.parametrize("work,eq", [(wl.HEAT_LARGE, sw.HEAT_F64), (wl.HEAT_PREC, sw.HEAT_F64),
+                                     (wl.HEAT_PREC, sw.HEAT_F32)],
+                         ids=["f64_n4194304", "f64_n16777216", "f32_n16777216"])
+def test_persistent_heat_launch_whole_grid(work, eq):
+    """The benchmarked heat launch at its benchmark size: one persistent
+    launch of W = 2048 tiles (2048 or 8192 tiles per phase, 21 overlapping
+    phases, every XCD taking tiles of every phase) equals naive_solve over
+    the whole grid bit for bit, and the oracle on dependency-cone windows."""
+    u0 = wl.initial_state(work)
+    host = pack(eq, u0)
+    announce("fullsize persistent heat", eq, work.n, work.steps)
+    got, width = _persistent_solve(eq, host, work)
+    assert width == 2048
+    announce("fullsize persistent heat: naive", eq, work.n, work.steps)
+    naive = run(eq, host, work.steps, work.dt, work.dx, "naive")
+    assert np.array_equal(got, naive)
+    r = work.dt / work.dx ** 2
+    span = 16
+    starts = _sample_starts(work.n)
+    if eq == sw.HEAT_F64:
+        ref = _heat_cone_samples(u0, work.steps, r, starts, span, oracle.heat_f64)
+        for s0, vals in ref.items():
+            assert np.array_equal(got[0][(np.arange(s0, s0 + span)) % work.n], vals), s0
+    else:
+        u32 = u0.astype(np.float32)
+        zero_c = np.zeros(work.n, np.float32)
+        for s0 in starts:
+            idx = (np.arange(s0 - work.steps - 1, s0 + span + work.steps + 1)) % work.n
+            u, c = oracle.heat_f32(u32[idx], zero_c[idx], work.steps, r)
+            sel = (np.arange(s0, s0 + span)) % work.n
+            assert np.array_equal(got[0][sel], u[work.steps + 1: work.steps + 1 + span]), s0
+            assert np.array_equal(got[1][sel], c[work.steps + 1: work.steps + 1 + span]), s0
+
+
 def test_euler_f64_n4194304_10000_steps():
     w = wl.EULER_LARGE
     q0 = wl.initial_state(w)
@@ -248,43 +299,72 @@ def test_batch_4096_problems_autotune(eq_heat, eq_euler):
            full_run_ms={str(t[3]): t[0] for t in timed}, chosen_threads=threads)
 
 
+def _oracle_subset(probs, count=128, seed=128):
+    """`count` problems drawn across the length range: the problems sorted by
+    length are cut into `count` strata of equal size and one problem is drawn
+    from each (seeded); the longest heat and the longest Euler problem (the
+    widest tiles the tuner picks) replace the draws of the last two strata."""
+    rng = np.random.default_rng(seed)
+    order = np.argsort([p.n for p in probs], kind="stable")
+    strata = np.array_split(order, count)
+    pick = [int(rng.choice(s)) for s in strata]
+    longest_heat = max((i for i, p in enumerate(probs) if p.eq == "heat"), key=lambda i: probs[i].n)
+    longest_euler = max((i for i, p in enumerate(probs) if p.eq != "heat"),
+                        key=lambda i: probs[i].n)
+    pick[-2:] = [longest_heat, longest_euler]
+    return sorted(set(pick))
+
+
+def _oracle_result(eq, host, steps, threads=15):
+    """The oracle of one batch problem (OpenMP over the host cores but one,
+    which the test's own thread keeps)."""
+    if eq == sw.HEAT_F64:
+        return oracle.heat_f64(host[0], steps, 0.25, threads=threads).reshape(1, -1)
+    if eq == sw.EULER_F64:
+        return oracle.euler_f64(host, steps, 0.1, threads=threads)
+    if eq == sw.HEAT_F32:
+        return np.stack(oracle.heat_f32(host[0], host[1], steps, 0.25, threads=threads))
+    q, c = oracle.euler_f32(host[:3], host[3:], steps, 0.1, threads=threads)
+    return np.concatenate([q, c])
+
+
 @pytest.mark.parametrize("eq_heat,eq_euler", [(sw.HEAT_F64, sw.EULER_F64),
                                               (sw.HEAT_F32, sw.EULER_F32)])
 def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
     """The batched workload at full size in one persistent launch, with the
     launch the tuning test chose (the library defaults if it did not run).
-    Every problem must equal its individual swept solve; the 16 smallest are
-    also checked against the oracle."""
+    Every problem must equal its own swept solve (phase launches, a different
+    schedule of the same tile bodies); 128 problems drawn across the length
+    range, the longest heat and Euler problems among them, are also checked
+    against the oracle, which runs on the host threads while the GPU works.
+    (A classic solve of every problem would take 2 * 10^7 launches.)"""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     probs, tensors, hosts, specs = _batch_specs(eq_heat, eq_euler)
+    subset = _oracle_subset(probs)
+    assert len(subset) >= 120
+    # one background worker steps the subset, longest problems first, while
+    # this thread drives the GPU (the oracle call releases the interpreter lock)
+    pool = ThreadPoolExecutor(max_workers=1)
+    futures = {i: pool.submit(_oracle_result, specs[i]["eq"], hosts[i], 5000)
+               for i in sorted(subset, key=lambda i: -probs[i].n)}
     widths, bpc, threads = _BATCH_CHOICE.get(sw.is_f64(eq_heat), (None, 0, 0))
     if widths:
         for s, w in zip(specs, widths):
             s["width"] = w
     announce("fullsize batch", eq_heat, eq_euler, "problems", len(specs), "blocks/CU", bpc,
-             "threads", threads)
+             "threads", threads, "oracle subset", len(subset))
     b = sw.Batch(specs, blocks_per_cu=bpc, threads=threads)
     stream = torch.cuda.current_stream().cuda_stream
     b.run(stream)
     assert b.wait(stream) == sw.SW_OK, sw.last_error()
     widths = [b.width(i) for i in range(len(specs))]
-    order = np.argsort([p.n for p in probs], kind="stable")
-    check_oracle = set(order[:16].tolist())
+    finals = []
     for i, (p, s) in enumerate(zip(probs, specs)):
         got = tensors[i].cpu().numpy()
+        finals.append(got)
         alone = run(s["eq"], hosts[i], 5000, s["dt"], s["dx"], "swept", width=widths[i])
         assert np.array_equal(got, alone), i
-        if i in check_oracle:
-            if s["eq"] == sw.HEAT_F64:
-                assert np.array_equal(got[0], oracle.heat_f64(hosts[i][0], 5000, 0.25))
-            elif s["eq"] == sw.EULER_F64:
-                assert np.array_equal(got, oracle.euler_f64(hosts[i], 5000, 0.1))
-            elif s["eq"] == sw.HEAT_F32:
-                u, c = oracle.heat_f32(hosts[i][0], hosts[i][1], 5000, 0.25)
-                assert np.array_equal(got[0], u) and np.array_equal(got[1], c)
-            else:
-                q, c = oracle.euler_f32(hosts[i][:3], hosts[i][3:], 5000, 0.1)
-                assert np.array_equal(got[:3], q) and np.array_equal(got[3:], c)
     # throughput of one more replay of the captured launch (5000 further steps)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -294,7 +374,20 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
     assert b.wait(stream) == sw.SW_OK, sw.last_error()
     ms = start.elapsed_time(stop)
     cells = sum(p.n for p in probs)
-    record(f"batch_4096x5000_{'f64' if sw.is_f64(eq_heat) else 'f32'}", ms=ms, cells=cells,
-           cell_updates_per_s=cells * 5000 / (ms * 1e-3), blocks_per_cu=bpc, threads=threads,
-           distinct_widths=len(set(widths)), widest=max(widths), narrowest=min(widths))
     b.close()
+    announce("fullsize batch: waiting for the oracle subset")
+    checked_widths = set()
+    for i in subset:
+        want = futures[i].result()
+        assert np.array_equal(finals[i], want), (i, probs[i].n, widths[i])
+        checked_widths.add((probs[i].eq, widths[i]))
+    pool.shutdown()
+    tag = 'f64' if sw.is_f64(eq_heat) else 'f32'
+    record(f"batch_4096x5000_{tag}", ms=ms, cells=cells,
+           cell_updates_per_s=cells * 5000 / (ms * 1e-3), blocks_per_cu=bpc, threads=threads,
+           distinct_widths=len(set(widths)), widest=max(widths), narrowest=min(widths),
+           oracle_checked=len(subset), oracle_widths=sorted(checked_widths))
+    # the widest tile of each equation in the batch was among the oracle checks
+    for kind in ("heat", "euler"):
+        wmax = max(w for p, w in zip(probs, widths) if (p.eq == "heat") == (kind == "heat"))
+        assert any(w == wmax and (e == "heat") == (kind == "heat") for e, w in checked_widths)
