@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the swept-rule hot path on one MI355X.
 
-One benchmark step is one full solve of the workload through the C ABI:
-every phase of the swept schedule -- Up Triangle, Diamonds, Down Triangle --
-over the whole grid for all its time steps.  Two schedules of the same
-phases exist: one kernel launch per phase (``swept_solve``), or one
-persistent launch that overlaps consecutive phases tile by tile (the batched
-launch with the single problem, ``sw_batch_run``).  By default the heat
-workloads of 2^20 cells and more use the persistent launch and the others
-the phase launches, the faster of the two for each on MI355X.  The default workload is
-the 1D heat equation (FTCS, binary64) on 2^22 periodic cells, r = 1/4,
-seeded random-mode initial condition, 20000 time steps.
+One benchmark step is one full solve of a workload through the C ABI: every
+phase of the swept schedule -- Up Triangle, Diamonds, Down Triangle -- over
+the whole grid for all its time steps.  The default run measures the
+2^24-cell configuration (the largest single-GPU one) in every equation and
+precision: the heat equation (FTCS, r = 1/4, seeded random-mode initial
+condition) and the Euler equations (Sod tiles of 2^14 cells, dt/dx = 0.1),
+binary64 and binary32 + Kahan, the Euler equations in both sub-step layouts,
+20000 time steps each.  The headline value is heat binary64; every leg
+reports swept and classic (one launch per sub-step) throughput, their ratio,
+its sampled error against the oracle and its rooflines.
 
-Prints ONE JSON line: the swept throughput in cell-updates/s (value), the
-classic one-launch-per-step throughput on the same workload, the roofline
-of the dominant kernel (timed live with HIP events on the library's stream)
-and the plain CPU oracle timed on a bounded sample of the same workload.
-Inputs are resident in HBM before the timed region starts.
+Heat grids of 2^20 cells and more run as one persistent launch per solve
+(the batched launch holding the single problem, ``sw_batch_run``), the other
+workloads one launch per phase (``swept_solve``), the faster schedule of each
+on MI355X.  Every timed solve starts from the initial state, restored from a
+device copy outside the timed region; times are HIP events on the launch
+stream and the reported time is the median over the timed solves.
+
+Prints ONE JSON line.  Inputs are resident in HBM when the timed region
+starts.
 """
 from __future__ import annotations
 
@@ -35,8 +39,17 @@ import paper_1811_08282_amd as sw  # noqa: E402
 from paper_1811_08282_amd import workloads as wl  # noqa: E402
 
 METRIC = "cell-updates/s swept vs naive (FP64, FP32) at stated error; % HBM roofline"
+CUS, CLOCK_HZ = 256, 2.4e9
 HBM_PEAK_GBS = 8000.0
-FP64_VECTOR_TFLOPS = 78.6  # counts an FMA as two flops
+# published vector peaks (an FMA counts as two flops; the kernels use no FMA
+# and no packed math, and every other operation counts as one flop)
+VECTOR_PEAK_TFLOPS = {True: 78.6, False: 157.3}  # binary64, binary32
+# LDS rates per compute unit and clock measured on gfx950 by a streaming
+# microbenchmark (the best width of each direction: ds_read_b128 and
+# ds_write_b128); the port is taken to serve reads and writes one at a time
+LDS_READ_B_PER_CLK = 150.4
+LDS_WRITE_B_PER_CLK = 70.9
+VALU_ISSUE_PER_S = CUS * CLOCK_HZ  # one wave instruction per clock per CU
 
 WORKLOADS = {
     "heat_f64_large": (wl.HEAT_LARGE, sw.HEAT_F64),
@@ -50,6 +63,10 @@ WORKLOADS = {
     "euler_f32_flat_prec": (wl.EULER_PREC, sw.EULER_F32_FLAT),
     "euler_f64_flat_prec": (wl.EULER_PREC, sw.EULER_F64_FLAT),
 }
+# the default run: the 2^24-cell configuration in every equation id; the first
+# leg is the headline value
+DEFAULT_LEGS = ["heat_f64_prec", "heat_f32_prec", "euler_f64_prec", "euler_f32_prec",
+                "euler_f64_flat_prec", "euler_f32_flat_prec"]
 
 # algorithmic bytes of the swept working struct per cell (read + write per phase)
 STRUCT_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 12, sw.EULER_F64: 56, sw.EULER_F32: 44,
@@ -67,14 +84,10 @@ NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32
 # binary32 adds three Kahan operations per component in the corrector.
 OPS_PER_UPDATE = {sw.HEAT_F64: 5, sw.HEAT_F32: 8, sw.EULER_F64: 162, sw.EULER_F32: 171,
                   sw.EULER_F64_FLAT: 162, sw.EULER_F32_FLAT: 171}
-# vector lane-operation issue rate with no fused or packed forms (the kernels
-# use neither): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# LDS port: 128 bytes per clock per CU
-LDS_PEAK_GBS = 256 * 128 * 2.4e9 / 1e9
-# LDS bytes per heat cell-update of the level sweep: three neighbour reads and
-# one write (binary32: plus the compensation read and write)
-LDS_BYTES_PER_UPDATE = {sw.HEAT_F64: 32, sw.HEAT_F32: 24}
+# LDS bytes per heat cell-update of the level sweep (read, write): three
+# neighbour reads and one write; binary32 also reads and writes the
+# compensation
+LDS_BYTES_PER_UPDATE = {sw.HEAT_F64: (24, 8), sw.HEAT_F32: (16, 8)}
 PROFILES = os.path.join(ROOT, "profiles")
 # the persistent launch of a heat-only batch (its kernel compiles only the heat body)
 PERSISTENT_SOURCES = ["batch.hip", "batch.h", "tile_heat.h", "geom.h", "tile_job.h"]
@@ -98,15 +111,21 @@ def kernel_source_hash(eq, schedule="phases") -> str:
     return h.hexdigest()
 
 
+def leg_label(work, eq) -> str:
+    """Name of a workload run in one equation id: <eq>_<precision>_n<N>_s<steps>."""
+    layout = "_flattened" if eq in (sw.EULER_F64_FLAT, sw.EULER_F32_FLAT) else ""
+    prec = "f64" if sw.is_f64(eq) else "f32"
+    return f"{work.eq}_{prec}_n{work.n}_s{work.steps}{layout}"
+
+
 def measured_counters(work, eq, width, threads, schedule="phases"):
     """Per-launch hardware counters of the swept kernel taken with rocprofv3 on
-    this workload (profiles/<workload>_phase_counters.txt for the phase
-    launches, <workload>_persistent_counters.txt for the persistent launch),
+    this workload (profiles/<label>_phase_counters.txt for the phase
+    launches, <label>_persistent_counters.txt for the persistent launch),
     or None when absent or taken on other kernel sources or another launch
     (width, workgroup size)."""
-    layout = "_flattened" if eq in (sw.EULER_F64_FLAT, sw.EULER_F32_FLAT) else ""
     kind = "persistent" if schedule == "persistent" else "phase"
-    path = os.path.join(PROFILES, f"{work.name}{layout}_{kind}_counters.txt")
+    path = os.path.join(PROFILES, f"{leg_label(work, eq)}_{kind}_counters.txt")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -132,78 +151,6 @@ def pack_state(eq, q):
     return np.concatenate([q.astype(np.float32), np.zeros(q.shape, np.float32)])
 
 
-def time_solves(torch, eq, state0, work, method, width, reps, warmup, threads=0):
-    """Mean ms per solve over `reps` solves (events on the library's stream)."""
-    dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width,
-                 threads=threads)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width,
-                 threads=threads)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3
-    return start.elapsed_time(stop) / reps, wall / reps
-
-
-def _batch_problem(eq, dev, work, width):
-    return dict(eq=eq, width=width, n_cells=work.n, n_steps=work.steps, dt=work.dt, dx=work.dx,
-                d_state=dev.data_ptr())
-
-
-def time_persistent(torch, eq, state0, work, width, threads, reps, warmup):
-    """Mean ms per solve over `reps` persistent launches of the batch holding
-    the single problem (events on torch's current stream, the launch stream);
-    also returns the width the batch chose."""
-    dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
-    torch.cuda.synchronize()
-    b = sw.Batch([_batch_problem(eq, dev, work, width)], threads=threads)
-    stream = torch.cuda.current_stream()
-    handle = stream.cuda_stream
-    for _ in range(warmup):
-        b.run(handle)
-    if b.wait(handle) != sw.SW_OK:
-        raise RuntimeError(sw.last_error())
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.run(handle)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3
-    if b.wait(handle) != sw.SW_OK:
-        raise RuntimeError(sw.last_error())
-    chosen = b.width(0)
-    b.close()
-    return start.elapsed_time(stop) / reps, wall / reps, chosen
-
-
-def solve_once(torch, eq, state0, work, width, threads, schedule):
-    """One solve from state0 on the given schedule; returns the device tensor."""
-    dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
-    if schedule == "persistent":
-        torch.cuda.synchronize()
-        b = sw.Batch([_batch_problem(eq, dev, work, width)], threads=threads)
-        handle = torch.cuda.current_stream().cuda_stream
-        b.run(handle)
-        if b.wait(handle) != sw.SW_OK:
-            raise RuntimeError(sw.last_error())
-        b.close()
-    else:
-        sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width,
-                 threads=threads)
-    return dev
-
-
 def _rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
@@ -223,6 +170,17 @@ def _heat_windows(u0, steps, r, starts, span, fn):
     return out
 
 
+_ORACLE_RESULTS = {}
+
+
+def _oracle_cached(key, compute):
+    """One oracle run per (workload, kind) per process: the two Euler layouts
+    compute the same arithmetic and are checked against the same result."""
+    if key not in _ORACLE_RESULTS:
+        _ORACLE_RESULTS[key] = compute()
+    return _ORACLE_RESULTS[key]
+
+
 def verify_sample(work, eq, gpu):
     """Sampled comparison of one full-size GPU solve with the oracle.
 
@@ -235,6 +193,7 @@ def verify_sample(work, eq, gpu):
     import oracle
     q0 = wl.initial_state(work)
     out = {"reference": "oracle"}
+    cached = _oracle_cached
     if eq in (sw.HEAT_F64, sw.HEAT_F32):
         r = work.dt / (work.dx * work.dx)
         span = 16
@@ -242,20 +201,22 @@ def verify_sample(work, eq, gpu):
         cells = lambda s0: np.arange(s0, s0 + span) % work.n  # noqa: E731
         sl = slice(work.steps + 1, work.steps + 1 + span)
         if eq == sw.HEAT_F64:
-            ref = _heat_windows(q0, work.steps, r, starts, span, oracle.heat_f64)
+            ref = cached((work.name, "heat_f64"),
+                         lambda: _heat_windows(q0, work.steps, r, starts, span, oracle.heat_f64))
             got = np.concatenate([gpu[0][cells(s0)] for s0, _ in ref])
             want = np.concatenate([v[sl] for _, v in ref])
             out["bit_exact"] = bool(np.array_equal(got, want))
         else:
             u32 = q0.astype(np.float32)
             pair = np.stack([u32, np.zeros_like(u32)])
-            ref = _heat_windows(pair, work.steps, r, starts, span,
-                                lambda w, k, a: np.stack(oracle.heat_f32(w[0], w[1], k, a)))
+            ref = cached((work.name, "heat_f32"), lambda: _heat_windows(
+                pair, work.steps, r, starts, span,
+                lambda w, k, a: np.stack(oracle.heat_f32(w[0], w[1], k, a))))
             got = np.concatenate([gpu[:, cells(s0)] for s0, _ in ref], axis=1)
             want = np.concatenate([v[:, sl] for _, v in ref], axis=1)
             out["bit_exact"] = bool(np.array_equal(got, want))
-            ref64 = _heat_windows(u32.astype(np.float64), work.steps, r, starts, span,
-                                  oracle.heat_f64)
+            ref64 = cached((work.name, "heat_f64_from_f32"), lambda: _heat_windows(
+                u32.astype(np.float64), work.steps, r, starts, span, oracle.heat_f64))
             want64 = np.concatenate([v[sl] for _, v in ref64])
             out["rel_inf_vs_binary64"] = _rel(got[0], want64)
         out["max_abs_diff"] = float(np.max(np.abs(np.asarray(got, np.float64)
@@ -266,18 +227,20 @@ def verify_sample(work, eq, gpu):
     tile = q0[:, : work.tile]
     tiles = work.n // work.tile
     if sw.is_f64(eq):
-        want = oracle.euler_f64(tile, work.steps, lam)
+        want = cached((work.name, "euler_f64"), lambda: oracle.euler_f64(tile, work.steps, lam))
         got = gpu.reshape(3, tiles, work.tile)
         out["bit_exact"] = bool(np.array_equal(got, np.broadcast_to(want[:, None, :], got.shape)))
         out["max_abs_diff"] = float(np.max(np.abs(got - want[:, None, :])))
     else:
         t32 = tile.astype(np.float32)
-        want_q, want_c = oracle.euler_f32(t32, np.zeros_like(t32), work.steps, lam)
+        want_q, want_c = cached((work.name, "euler_f32"), lambda: oracle.euler_f32(
+            t32, np.zeros_like(t32), work.steps, lam))
         want = np.concatenate([want_q, want_c])
         got = gpu.reshape(6, tiles, work.tile)
         out["bit_exact"] = bool(np.array_equal(got, np.broadcast_to(want[:, None, :], got.shape)))
         out["max_abs_diff"] = float(np.max(np.abs(got.astype(np.float64) - want[:, None, :])))
-        ref64 = oracle.euler_f64(t32.astype(np.float64), work.steps, lam)
+        ref64 = cached((work.name, "euler_f64_from_f32"), lambda: oracle.euler_f64(
+            t32.astype(np.float64), work.steps, lam))
         g0 = got[:3, 0, :].astype(np.float64)
         out["rel_inf_vs_binary64"] = {k: _rel(g0[i], ref64[i]) for i, k in enumerate("rho m E".split())}
         out["rel_1_vs_binary64"] = {
@@ -287,10 +250,9 @@ def verify_sample(work, eq, gpu):
     return out
 
 
-def cpu_baseline(work, eq, budget_s, gpu_final=None):
+def cpu_baseline(work, eq, budget_s):
     """The oracle as it stands on the host cores, on a bounded sample of the
-    workload; with `gpu_final` (one full-size GPU solve from the same input)
-    the same leg also checks that solve against the oracle on a sample."""
+    workload (whole time steps of the whole grid until the budget is spent)."""
     import oracle
     q = wl.initial_state(work)
     chunk = 20
@@ -354,10 +316,6 @@ def cpu_baseline(work, eq, budget_s, gpu_final=None):
                                 "cores": 1,
                                 "sample": f"the whole workload, {work.n} cells x {work.steps} "
                                           f"time steps, {t1 * 1e3:.1f} ms"}
-    if gpu_final is not None:
-        t0 = time.perf_counter()
-        out["verify"] = verify_sample(work, eq, gpu_final)
-        out["verify"]["seconds"] = time.perf_counter() - t0
     return out
 
 
@@ -372,22 +330,258 @@ def cpu_model() -> str:
     return "unknown CPU"
 
 
+# ---- timing --------------------------------------------------------------------
+
+def _problem(eq, dev, work, width):
+    return dict(eq=eq, width=width, n_cells=work.n, n_steps=work.steps, dt=work.dt, dx=work.dx,
+                d_state=dev.data_ptr())
+
+
+def time_solves(torch, eq, state0, work, method, schedule, width, threads, reps, warmup,
+                warmup_steps=None):
+    """Time `reps` solves of the workload, each from the initial state
+    restored by a device copy outside the timed region (HIP events on the
+    launch stream, which is torch's current stream).  Returns the median ms,
+    every ms, the device tensor holding the last solve's final state, and the
+    width used."""
+    import statistics
+    pristine = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
+    dev = pristine.clone()
+    stream = torch.cuda.current_stream()
+    handle = stream.cuda_stream
+    batch = None
+    if method == "swept" and schedule == "persistent":
+        torch.cuda.synchronize()
+        batch = sw.Batch([_problem(eq, dev, work, width)], threads=threads)
+        width = batch.width(0)
+
+        def run(steps=None):
+            batch.run(handle)
+    else:
+        def run(steps=None):
+            sw.solve(eq, dev, work.steps if steps is None else steps, work.dt, work.dx,
+                     method=method, width=width, threads=threads)
+    for _ in range(warmup):
+        dev.copy_(pristine)
+        run(warmup_steps)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        dev.copy_(pristine)
+        start.record(stream)
+        run()
+        stop.record(stream)
+        stop.synchronize()
+        times.append(start.elapsed_time(stop))
+    if batch is not None:
+        if batch.wait(handle) != sw.SW_OK:
+            raise RuntimeError(sw.last_error())
+        batch.close()
+    torch.cuda.synchronize()
+    del pristine
+    return statistics.median(times), times, dev, width
+
+
+def paper_style_ms(torch, eq, state0, work, method, schedule, width, threads):
+    """One solve timed the way the paper times (Sec. 5): device allocation,
+    the host-to-device copy of the state, the solve and the copy back."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
+    if schedule == "persistent":
+        handle = torch.cuda.current_stream().cuda_stream
+        b = sw.Batch([_problem(eq, dev, work, width)], threads=threads)
+        b.run(handle)
+        if b.wait(handle) != sw.SW_OK:
+            raise RuntimeError(sw.last_error())
+        b.close()
+    else:
+        sw.solve(eq, dev, work.steps, work.dt, work.dx, method=method, width=width,
+                 threads=threads)
+    dev.cpu()
+    return (time.perf_counter() - t0) * 1e3
+
+
+# ---- rooflines -------------------------------------------------------------------
+
+def rooflines(work, eq, schedule, width, threads, ms, rate):
+    """Fractions of every unit that could bind the swept kernel, from the
+    algorithmic counts and, where a counter record of the exact kernel
+    sources and launch is committed under profiles/, from the counters.
+    The binding unit is the one nearest its ceiling."""
+    rad = sw.radius(eq)
+    phases = sw.sw_phase_count(work.steps * sw.substeps(eq), width, rad)
+    launches = 1 if schedule == "persistent" else phases
+    launch_ms = ms / launches
+    updates_per_launch = work.n * work.steps / launches
+    tiles = work.n // width
+    alg_bytes = (phases // launches) * tiles * ((width + 2 * rad) + width) * STRUCT_BYTES[eq]
+    hbm_gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
+    units = {}
+    units["hbm"] = {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": hbm_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes}
+    f64 = sw.is_f64(eq)
+    ops = OPS_PER_UPDATE[eq]
+    peak_alu = VECTOR_PEAK_TFLOPS[f64]
+    units["alu"] = {"achieved": rate * ops / 1e12, "peak": peak_alu, "unit": "TFLOP/s",
+                    "frac": rate * ops / 1e12 / peak_alu, "flops_per_cell_update": ops,
+                    "precision": "binary64" if f64 else "binary32"}
+    counters = measured_counters(work, eq, width, threads, schedule)
+    rd = wr = None
+    source = None
+    if counters and counters.get("lds_load_bytes_per_launch") is not None:
+        rd = counters["lds_load_bytes_per_launch"] / updates_per_launch
+        wr = counters["lds_store_bytes_per_launch"] / updates_per_launch
+        source = "counters"
+    elif eq in LDS_BYTES_PER_UPDATE:
+        rd, wr = LDS_BYTES_PER_UPDATE[eq]
+        source = "algorithmic"
+    if rd is not None:
+        # seconds of port time per second: reads and writes one at a time,
+        # each at its measured best rate
+        busy = rate * (rd / (LDS_READ_B_PER_CLK * CUS * CLOCK_HZ)
+                       + wr / (LDS_WRITE_B_PER_CLK * CUS * CLOCK_HZ))
+        achieved = rate * (rd + wr) / 1e9
+        units["lds"] = {"achieved": achieved, "peak": achieved / busy, "unit": "GB/s",
+                        "frac": busy, "read_bytes_per_cell_update": rd,
+                        "write_bytes_per_cell_update": wr, "source": source,
+                        "peak_model": f"reads at {LDS_READ_B_PER_CLK} B/clk/CU and writes at "
+                                      f"{LDS_WRITE_B_PER_CLK} B/clk/CU (measured), in turn"}
+    if counters and counters.get("valu_insts_per_launch"):
+        issue = counters["valu_insts_per_launch"] / (launch_ms * 1e-3)
+        units["valu_issue"] = {
+            "achieved": issue / 1e9, "peak": VALU_ISSUE_PER_S / 1e9, "unit": "G wave-insts/s",
+            "frac": issue / VALU_ISSUE_PER_S,
+            "insts_per_cell_update": counters["valu_insts_per_launch"] * 64 / updates_per_launch}
+    bound = max(units, key=lambda k: units[k]["frac"])
+    traffic = counters.get("hbm_bytes_per_launch") if counters else None
+    kernel = ("persistent swept kernel (heat body alone)" if schedule == "persistent"
+              else "swept phase kernel")
+    out = {"bound": bound, "achieved": units[bound]["achieved"], "peak": units[bound]["peak"],
+           "unit": units[bound]["unit"], "frac": units[bound]["frac"], "traffic": traffic,
+           "kernel": kernel, "launch_ms": launch_ms, "launches_per_step": launches,
+           "counters": "profiles/" + f"{leg_label(work, eq)}_"
+                       f"{'persistent' if schedule == 'persistent' else 'phase'}_counters.txt"
+                       if counters else None}
+    out.update(units)
+    return out
+
+
+# ---- one leg: swept and classic on one workload in one equation id ---------------
+
+def default_schedule(eq, work):
+    # measured on MI355X: one persistent launch wins for heat grids of 2^20
+    # cells and more (2^22: 2.12e12 against 1.98e12 cell-updates/s); on a grid
+    # of a few tiles the phase launches are slightly faster, and for Euler
+    # the two are level or the phase launches win
+    big_heat = eq in (sw.HEAT_F64, sw.HEAT_F32) and work.n >= (1 << 20)
+    return "persistent" if big_heat else "phases"
+
+
+def run_leg(torch, work, eq, args, reps, naive_reps, warmup, verify=True):
+    schedule = args.schedule if args.schedule != "auto" else default_schedule(eq, work)
+    state0 = pack_state(eq, wl.initial_state(work))
+    updates = work.n * work.steps
+    if schedule == "persistent":
+        width, threads = args.width, args.threads or 256
+    else:
+        width = args.width or sw.sw_default_width(eq, work.n)
+        threads = args.threads or sw.sw_default_threads(eq, width)
+    # a short warm-up solve is enough for the slow legs (it loads the code
+    # and sizes the working arrays); the persistent launch always runs whole
+    warm_steps = None if (schedule == "persistent" or work.eq == "heat") else min(work.steps, 100)
+    label = leg_label(work, eq)
+    log(f"[bench] {label}: swept ({schedule}), {reps} timed solves")
+    ms, times, dev, width = time_solves(torch, eq, state0, work, "swept", schedule, width,
+                                        threads, reps, warmup, warm_steps)
+    phases = sw.sw_phase_count(work.steps * sw.substeps(eq), width, sw.radius(eq))
+    rate = updates / (ms * 1e-3)
+    log(f"[bench] {label}: swept {ms:.3f} ms/solve ({rate:.4g} cell-updates/s), W={width}, "
+        f"threads={threads}, phases={phases}")
+    final = dev.cpu().numpy()
+    del dev
+    leg = {"workload": label, "eq": eq, "precision": "binary64" if sw.is_f64(eq) else "binary32",
+           "n_cells": work.n, "time_steps": work.steps, "width": width, "threads": threads,
+           "schedule": schedule, "phases": phases,
+           "swept": {"value": rate, "ms_per_solve": ms, "ms_all": times, "reps": reps}}
+    if naive_reps:
+        log(f"[bench] {label}: naive, {naive_reps} timed solves")
+        nms, ntimes, ndev, _ = time_solves(torch, eq, state0, work, "naive", "phases", 0, 0,
+                                           naive_reps, 1, 10)
+        del ndev
+        nrate = updates / (nms * 1e-3)
+        log(f"[bench] {label}: naive {nms:.3f} ms/solve ({nrate:.4g} cell-updates/s)")
+        leg["naive"] = {"value": nrate, "ms_per_solve": nms, "ms_all": ntimes, "reps": naive_reps,
+                        "launches_per_solve": work.steps * sw.substeps(eq),
+                        "hbm_roofline_value": HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]}
+        leg["swept_over_naive"] = rate / nrate
+    leg["effective_roofline_frac"] = rate / (HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq])
+    leg["roofline"] = rooflines(work, eq, schedule, width, threads, ms, rate)
+    if verify:
+        t0 = time.perf_counter()
+        v = verify_sample(work, eq, final)
+        v["seconds"] = time.perf_counter() - t0
+        leg["error_vs_oracle"] = v
+        log(f"[bench] {label}: oracle check bit_exact={v['bit_exact']}")
+    return leg, state0
+
+
+# ---- width sweep -----------------------------------------------------------------
+
+def width_sweep(torch, work, eq, widths, reps, naive_reps):
+    """Swept (phase launches and the persistent launch) at every width, and
+    classic once, on one workload; every solve from the restored state."""
+    state0 = pack_state(eq, wl.initial_state(work))
+    updates = work.n * work.steps
+    rows = []
+    for w in widths:
+        row = {"width": w}
+        threads = sw.sw_default_threads(eq, w)
+        ms, times, dev, _ = time_solves(torch, eq, state0, work, "swept", "phases", w, threads,
+                                        reps, 1)
+        del dev
+        row["phases"] = {"value": updates / (ms * 1e-3), "ms_per_solve": ms, "threads": threads,
+                         "launches": sw.sw_phase_count(work.steps * sw.substeps(eq), w,
+                                                       sw.radius(eq))}
+        if eq in (sw.HEAT_F64, sw.HEAT_F32) and w >= 64:
+            pms, _, dev, _ = time_solves(torch, eq, state0, work, "swept", "persistent", w, 256,
+                                         reps, 1)
+            del dev
+            row["persistent"] = {"value": updates / (pms * 1e-3), "ms_per_solve": pms,
+                                 "threads": 256}
+        log(f"[bench] sweep W={w}: {json.dumps(row)}")
+        rows.append(row)
+    nms, _, dev, _ = time_solves(torch, eq, state0, work, "naive", "phases", 0, 0, naive_reps, 1)
+    del dev
+    return {"workload": leg_label(work, eq), "reps": reps, "rows": rows,
+            "naive": {"value": updates / (nms * 1e-3), "ms_per_solve": nms, "reps": naive_reps}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed solves")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
-    ap.add_argument("--workload", default="heat_f64_large", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=5,
+                    help="timed solves of the headline workload (median reported)")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves before the timed ones")
+    ap.add_argument("--workload", default=None, choices=sorted(WORKLOADS),
+                    help="measure one workload only (default: every leg at 2^24 cells)")
     ap.add_argument("--width", type=int, default=0, help="triangle width (0: library choice)")
     ap.add_argument("--threads", type=int, default=0,
                     help="workgroup size of the swept kernel (0: library choice)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "phases", "persistent"],
                     help="one launch per phase, or one persistent launch per solve "
                          "(auto: persistent for heat grids of 2^20 cells and more)")
-    ap.add_argument("--naive-reps", type=int, default=1)
+    ap.add_argument("--naive-reps", type=int, default=3, help="timed classic solves of heat legs")
+    ap.add_argument("--euler-reps", type=int, default=1,
+                    help="timed swept and classic solves of each Euler leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-naive", action="store_true", help="skip the classic-path timing")
+    ap.add_argument("--no-verify", action="store_true", help="skip the sampled oracle checks")
+    ap.add_argument("--sweep", default=None, choices=["c2", "c1"],
+                    help="width sweep of the 2^22-cell heat workload (c2, widths 64 to the LDS "
+                         "limit) or the 1024-cell one at W = 64 (c1)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -412,114 +606,44 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}))
         return 0
-    work, eq = WORKLOADS[args.workload]
     sw.load()
-    schedule = args.schedule
-    if schedule == "auto":
-        # measured on MI355X: the persistent launch wins for heat grids of
-        # 2^20 cells and more (2^22: 2.12e12 against 1.98e12); on a grid of
-        # a few tiles (1024 cells) the phase launches are slightly faster, and
-        # for Euler the two are level or the phase launches win
-        big_heat = eq in (sw.HEAT_F64, sw.HEAT_F32) and work.n >= (1 << 20)
-        schedule = "persistent" if big_heat else "phases"
-    state0 = pack_state(eq, wl.initial_state(work))
-    updates = work.n * work.steps
-    if schedule == "persistent":
-        threads = args.threads or 256
-        ms, wall_ms, width = time_persistent(torch, eq, state0, work, args.width, threads,
-                                             args.steps, args.warmup)
-    else:
-        width = args.width or sw.sw_default_width(eq, work.n)
-        threads = args.threads or sw.sw_default_threads(eq, width)
-    final_level = work.steps * sw.substeps(eq)
-    phases = sw.sw_phase_count(final_level, width, sw.radius(eq))
-    log(f"[bench] workload {work.name} eq={eq} W={width} threads={threads} phases={phases} "
-        f"schedule={schedule}")
-    if schedule == "phases":
-        ms, wall_ms = time_solves(torch, eq, state0, work, "swept", width, args.steps,
-                                  args.warmup, threads)
-    log(f"[bench] swept {ms:.3f} ms/solve ({updates / ms * 1e3:.4g} cell-updates/s)")
-    phase_launches = None
-    if schedule == "persistent":
-        # the same solve through swept_solve (one launch per phase), for reference
-        pw = sw.sw_default_width(eq, work.n)
-        pt = sw.sw_default_threads(eq, pw)
-        pms, _ = time_solves(torch, eq, state0, work, "swept", pw, args.steps, args.warmup, pt)
-        phase_launches = {"value": updates / (pms * 1e-3), "ms_per_step": pms, "width": pw,
-                          "threads": pt, "launches_per_step": sw.sw_phase_count(
-                              work.steps * sw.substeps(eq), pw, sw.radius(eq))}
-        log(f"[bench] swept, one launch per phase {pms:.3f} ms/solve "
-            f"({updates / pms * 1e3:.4g} cell-updates/s)")
-    naive_ms = float("nan")
-    if not args.no_naive:
-        naive_ms, _ = time_solves(torch, eq, state0, work, "naive", 0, args.naive_reps, 1)
-        log(f"[bench] naive {naive_ms:.3f} ms/solve ({updates / naive_ms * 1e3:.4g} cell-updates/s)")
 
-    # the paper's timing protocol also counts device allocation and the copies
-    # to and from the host; reported beside the HBM-resident figure only
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dev = solve_once(torch, eq, state0, work, width, threads, schedule)
-    host_final = dev.cpu().numpy()
-    paper_ms = (time.perf_counter() - t0) * 1e3
-    del dev, host_final
+    if args.sweep:
+        if args.sweep == "c2":
+            work, eq = wl.HEAT_LARGE, sw.HEAT_F64
+            wmax = sw.sw_max_width(eq)
+            widths = [w for w in (64, 128, 256, 512, 1024, 2048, 4096, 8192) if w <= wmax]
+            res = width_sweep(torch, work, eq, widths, max(args.steps, 1), 1)
+        else:
+            work, eq = wl.HEAT_SMALL, sw.HEAT_F64
+            res = width_sweep(torch, work, eq, [64], max(args.steps, 1), max(args.steps, 1))
+        res["metric"] = "cell-updates/s"
+        print(json.dumps(res), flush=True)
+        return 0
 
-    value = updates / (ms * 1e-3)
-    naive_value = updates / (naive_ms * 1e-3) if naive_ms == naive_ms else None
-    # dominant kernel: the swept phase kernel (one launch per phase) or the
-    # persistent kernel (one launch per solve, every phase inside)
-    launches = 1 if schedule == "persistent" else phases
-    launch_ms = ms / launches
-    tiles = work.n // width
-    alg_bytes = (phases // launches) * tiles * ((width + 2 * sw.radius(eq)) + width) \
-        * STRUCT_BYTES[eq]
-    achieved_gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
-    hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved_gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg_bytes}
-    counters = measured_counters(work, eq, width, threads, schedule)
-    traffic = counters.get("hbm_bytes_per_launch") if counters else None
-    ops = OPS_PER_UPDATE[eq]
-    achieved = value * ops / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
-                "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                "ops_per_cell_update": ops, "flops_per_launch": updates * ops / launches,
-                "kernel": ("persistent swept kernel (heat body alone)" if schedule == "persistent"
-                           else "swept phase kernel"),
-                "launch_ms": launch_ms, "launches_per_step": launches, "hbm": hbm}
-    if eq in LDS_BYTES_PER_UPDATE:
-        lds_gbs = value * LDS_BYTES_PER_UPDATE[eq] / 1e9
-        roofline["lds"] = {"achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                           "frac": lds_gbs / LDS_PEAK_GBS,
-                           "bytes_per_cell_update": LDS_BYTES_PER_UPDATE[eq]}
-    if counters and counters.get("lds_load_bytes_per_launch") is not None:
-        # LDS bytes the SQ counters saw (64-byte units of the load and store
-        # bandwidth counters), per cell-update and per second of launch time
-        lds_bytes = counters["lds_load_bytes_per_launch"] + counters["lds_store_bytes_per_launch"]
-        measured = {"bytes_per_cell_update": lds_bytes / (updates / launches),
-                    "achieved": lds_bytes / (launch_ms * 1e-3) / 1e9, "peak": LDS_PEAK_GBS,
-                    "unit": "GB/s"}
-        measured["frac"] = measured["achieved"] / LDS_PEAK_GBS
-        roofline.setdefault("lds", {})["measured"] = measured
-    # the unit that binds the kernel, from the counter profile and the LDS
-    # probe: the heat level sweep saturates the LDS port (its measured
-    # pattern ceiling is 3.39 updates per clock per CU), the Euler kernels
-    # the VALU issue (correctly rounded divisions and square roots)
-    roofline["binding_unit"] = "lds" if eq in LDS_BYTES_PER_UPDATE else "valu"
-    if counters and counters.get("valu_insts_per_launch"):
-        # wave-level VALU instructions issued per second over the chip's issue
-        # rate (one wave instruction per clock per CU)
-        rate = counters["valu_insts_per_launch"] / (launch_ms * 1e-3)
-        roofline["valu_issue"] = {
-            "insts_per_cell_update": counters["valu_insts_per_launch"] * 64 / (updates / launches),
-            "achieved": rate / 1e9, "peak": 256 * 2.4, "unit": "G wave-insts/s",
-            "frac": rate / (256 * 2.4e9)}
-    # with a counter profile, the unit nearer its ceiling binds (binary32 heat
-    # issues VALU instructions at 94 % of the chip's rate while its LDS port
-    # runs at 73 %)
-    lds_meas = roofline.get("lds", {}).get("measured")
-    if "valu_issue" in roofline and lds_meas:
-        roofline["binding_unit"] = ("valu" if roofline["valu_issue"]["frac"] > lds_meas["frac"]
-                                    else "lds")
+    legs_spec = ([(args.workload,) + WORKLOADS[args.workload]] if args.workload else
+                 [(name,) + WORKLOADS[name] for name in DEFAULT_LEGS])
+    legs = []
+    head_state0 = None
+    for i, (name, work, eq) in enumerate(legs_spec):
+        euler = work.eq == "euler"
+        if i == 0:
+            reps, warmup = args.steps, args.warmup
+        else:
+            reps, warmup = (args.euler_reps, 1) if euler else (min(args.steps, 5), 1)
+        naive_reps = 0 if args.no_naive else (args.euler_reps if euler else args.naive_reps)
+        leg, state0 = run_leg(torch, work, eq, args, reps, naive_reps, warmup,
+                              verify=not args.no_verify)
+        if i == 0:
+            head_state0 = state0
+        legs.append(leg)
+
+    head = legs[0]
+    name, work, eq = legs_spec[0]
+    ms = head["swept"]["ms_per_solve"]
+    value = head["swept"]["value"]
+    paper_ms = paper_style_ms(torch, eq, head_state0, work, "swept", head["schedule"],
+                              head["width"], head["threads"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -533,32 +657,24 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64" if sw.is_f64(eq) else "f32",
         "data": "synthetic",
-        "config": {"workload": work.name + ("_flattened" if eq in (sw.EULER_F64_FLAT, sw.EULER_F32_FLAT) else ""),
-                   "n_cells": work.n, "time_steps": work.steps, "width": width,
-                   "threads": threads, "schedule": schedule, "phases": phases,
-                   "method": "swept", "parallelism": "single-gpu"},
-        "swept_phase_launches": phase_launches,
-        "naive": {"value": naive_value, "ms_per_step": naive_ms,
-                  "hbm_roofline_value": HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]},
-        "swept_over_naive": value / naive_value if naive_value else None,
-        "effective_roofline_frac": value / (HBM_PEAK_GBS * 1e9 / NAIVE_BYTES[eq]),
-        "roofline": roofline,
-        "wall_ms_per_step": wall_ms,
-        "with_host_copies": {"ms_per_step": paper_ms, "value": updates / (paper_ms * 1e-3),
+        "config": {"workload": head["workload"], "n_cells": work.n, "time_steps": work.steps,
+                   "width": head["width"], "threads": head["threads"],
+                   "schedule": head["schedule"], "phases": head["phases"], "method": "swept",
+                   "parallelism": "single-gpu",
+                   "step": f"one solve: {work.steps} time steps of all {work.n} cells"},
+        "naive": head.get("naive"),
+        "swept_over_naive": head.get("swept_over_naive"),
+        "effective_roofline_frac": head["effective_roofline_frac"],
+        "roofline": head["roofline"],
+        "error_vs_oracle": head.get("error_vs_oracle"),
+        "with_host_copies": {"ms_per_step": paper_ms, "value": work.n * work.steps / (paper_ms * 1e-3),
                              "note": "one solve including device allocation and the host-to-device "
                                      "and device-to-host copies of the state (PCIe)"},
+        "legs": [{k: v for k, v in leg.items() if k != "eq"} for leg in legs],
     }
     if not args.no_cpu_baseline:
-        # one more solve from the same input, outside the timed region, for
-        # the sampled check against the oracle in the CPU leg
-        dev = solve_once(torch, eq, state0, work, width, threads, schedule)
-        torch.cuda.synchronize()
-        final = dev.cpu().numpy()
-        del dev
-        log("[bench] cpu baseline (oracle) and sampled check ...")
-        out["cpu_baseline"] = cpu_baseline(work, eq, args.cpu_seconds, final)
-        v = out["cpu_baseline"]["verify"]
-        out["error_vs_oracle"] = {k: v[k] for k in v if k not in ("seconds",)}
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(work, eq, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 
