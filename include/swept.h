@@ -134,8 +134,8 @@ int sw_max_width(int eq);
 /* The width swept_solve picks when none is given and the autotuner has
  * recorded none (see sw_tuned_width): the largest valid width (a multiple of
  * 2R dividing n_cells with n_cells / W >= 2) not above the preferred width
- * of `eq` -- heat binary64 1024, heat binary32 2048, Euler 1024 (flattened
- * binary32 2048), measured on MI355X.  0 when there is none. */
+ * of `eq` -- heat 2048, Euler 1024 (flattened binary32 2048), measured on
+ * MI355X.  0 when there is none. */
 int sw_default_width(int eq, int64_t n_cells);
 
 /* The workgroup size swept_solve uses for tile width `width` when none is

@@ -76,13 +76,13 @@ int struct_bytes(int eq)
     }
 }
 
-// measured on MI355X (2^22 cells binary64, 2^24 binary32): heat binary64
-// best at 1024, heat binary32 at 2048, Euler at 1024 with 512-thread
+// measured on MI355X (2^24 cells): heat best at 2048 in both precisions
+// (the register-blocked level sweep), Euler at 1024 with 512-thread
 // workgroups (flattened binary32 equally fast at 2048); sw_autotune refines
 // per grid size
 int preferred_width(int eq)
 {
-    if (eq == SW_HEAT_F32 || eq == SW_EULER_F32_FLAT)
+    if (!is_euler(eq) || eq == SW_EULER_F32_FLAT)
         return 2048;
     return 1024;
 }
@@ -115,7 +115,7 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int max_width(int eq)
 {
     const int step = 2 * radius(eq);
-    int64_t w = sw::kLdsBytes / lds_per_cell(eq) - 2 * radius(eq);
+    int64_t w = sw::kLdsBytes / lds_per_cell(eq) - sw::lds_tile_cells(!is_euler(eq), 0, radius(eq));
     if (w > kMaxWidth)
         w = kMaxWidth;
     return (int)(w - w % step);

@@ -120,7 +120,7 @@ hipError_t launch_by_threads(int nt, K64 k64, K128 k128, K256 k256, K512 k512, d
 hipError_t heat_f64_swept_phase(const PhaseLaunch &p, double *state, const double *ws_in,
                                 double *ws_out, double r, hipStream_t s)
 {
-    const size_t lds = (size_t)(p.w + 2) * kLdsPerCellHeatF64;
+    const size_t lds = (size_t)lds_tile_cells(true, p.w, 1) * kLdsPerCellHeatF64;
     return launch_by_threads(p.threads, k_heat_f64_phase<64>, k_heat_f64_phase<128>,
                              k_heat_f64_phase<256>, k_heat_f64_phase<512>, dim3((unsigned)(p.n / p.w)), lds, s, state,
                              ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, r,
@@ -144,7 +144,7 @@ hipError_t heat_f64_naive_step(const double *u, double *v, int64_t n, double r, 
 hipError_t heat_f32_swept_phase(const PhaseLaunch &p, float *state, const float *ws_in,
                                 float *ws_out, float r, hipStream_t s)
 {
-    const size_t lds = (size_t)(p.w + 2) * kLdsPerCellHeatF32;
+    const size_t lds = (size_t)lds_tile_cells(true, p.w, 1) * kLdsPerCellHeatF32;
     return launch_by_threads(p.threads, k_heat_f32_phase<64>, k_heat_f32_phase<128>,
                              k_heat_f32_phase<256>, k_heat_f32_phase<512>, dim3((unsigned)(p.n / p.w)), lds, s, state,
                              ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, r,

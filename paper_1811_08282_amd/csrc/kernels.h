@@ -19,6 +19,11 @@ constexpr int kStructBytesEulerF32 = 44;  // Q0[3], c[3], Q1[3] (f32), Pr (f64)
 constexpr int kStructBytesFlatF64 = 48;   // Q0[3], Q1[3]
 constexpr int kStructBytesFlatF32 = 36;   // Q0[3], c[3], Q1[3] (f32)
 
+// Cells of LDS padding beyond each halo of a heat tile: the ghost lanes of
+// the register-blocked level sweep read (unused) values up to one lane of
+// cells past the halo.
+constexpr int kHeatLdsPad = 5;
+
 // LDS bytes per tile cell of each swept kernel (struct + scratch).
 constexpr int kLdsPerCellHeatF64 = 16;
 constexpr int kLdsPerCellHeatF32 = 12;
@@ -26,6 +31,13 @@ constexpr int kLdsPerCellEulerF64 = 64;  // struct 56 + pressure 8
 constexpr int kLdsPerCellEulerF32 = 52;  // struct 44 + pressure 8
 constexpr int kLdsPerCellFlatF64 = 48;   // struct only: pressures, ratios, fluxes by lane shifts
 constexpr int kLdsPerCellFlatF32 = 36;   // struct only
+
+// LDS cells of one tile of width w with stencil radius `radius`: the tile, its
+// halos and, for heat, the padding.
+inline int lds_tile_cells(bool heat, int w, int radius)
+{
+    return w + 2 * radius + (heat ? 2 * kHeatLdsPad : 0);
+}
 
 // Description of one swept phase launch.
 struct PhaseLaunch {

@@ -32,6 +32,7 @@
 #include <math.h>
 
 #include "geom.h"
+#include "lanes.h"
 #include "tile_job.h"
 
 namespace sw {
@@ -49,34 +50,6 @@ __device__ __forceinline__ double limiter(double q)
 __device__ __forceinline__ double ratio(double pm, double pc, double pp)
 {
     return (pp - pc) / (pc - pm);
-}
-
-// lane l receives v of lane l+1 (lane 63 receives 0)
-__device__ __forceinline__ double from_next_lane(double v)
-{
-    const long long vi = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)vi, 0x130, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(vi >> 32), 0x130, 0xf, 0xf, true);
-    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
-}
-
-__device__ __forceinline__ float from_next_lane(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
-}
-
-// lane l receives v of lane l-1 (lane 0 receives 0)
-__device__ __forceinline__ double from_prev_lane(double v)
-{
-    const long long vi = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)vi, 0x138, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(vi >> 32), 0x138, 0xf, 0xf, true);
-    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
-}
-
-__device__ __forceinline__ float from_prev_lane(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
 constexpr int kFaceLanes = 63;  // cells a wave updates per pass (lane 63: face only)

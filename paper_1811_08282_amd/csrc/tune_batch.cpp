@@ -291,7 +291,8 @@ int prepare_batch(int n_problems, const sw_problem *problems, PreparedBatch *pb)
         pb->widths[i] = w;
         pb->array_off[i] = arrays;
         arrays += 2 * swept_copy_bytes(p.eq, p.n_cells);
-        pb->max_lds = std::max(pb->max_lds, (size_t)(w + 2 * b.radius) * (size_t)lds_per_cell(p.eq));
+        pb->max_lds = std::max(pb->max_lds, (size_t)sw::lds_tile_cells(!is_euler(p.eq), w, b.radius) *
+                                                (size_t)lds_per_cell(p.eq));
         all64 = all64 && p.eq == SW_HEAT_F64;
         all32 = all32 && p.eq == SW_HEAT_F32;
     }

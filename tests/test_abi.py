@@ -55,7 +55,7 @@ def test_width_limits():
         wmax = sw.sw_max_width(eq)
         assert wmax % (2 * rad) == 0 and (wmax + 2 * rad) * per_cell <= 160 * 1024
         assert wmax <= 8192
-    assert sw.sw_default_width(sw.HEAT_F64, 1 << 22) == 1024
+    assert sw.sw_default_width(sw.HEAT_F64, 1 << 22) == 2048
     assert sw.sw_default_width(sw.EULER_F64, 1 << 22) == 1024
     assert sw.sw_default_width(sw.EULER_F32, 1 << 24) == 1024
     assert sw.sw_default_width(sw.HEAT_F32, 1 << 24) == 2048

@@ -55,6 +55,30 @@ def test_heat_f64_swept_every_width(width):
         assert np.array_equal(got, want), (width, steps, rel_inf(got, want))
 
 
+# The heat level sweep runs in register blocks of four levels: rows of 62
+# lanes x 4 cells, a row aligned to each window edge (the right one stored
+# mirrored), LDS only between blocks, and a level-by-level fallback for
+# narrow windows.  Cases: several rows per wave, odd W/2 (odd level parity
+# at the phase starts), 64- to 512-thread workgroups, flat cuts at a step
+# count that is not a multiple of W/2, and W = 4096 in 256 threads, where
+# the widest windows need more rows than four waves hold and fall back.
+@pytest.mark.parametrize("eq", [sw.HEAT_F64, sw.HEAT_F32])
+@pytest.mark.parametrize("n,width,threads,steps", [
+    (3 * 2048, 2048, 256, 2 * 1024 + 517), (4 * 1030, 1030, 128, 1500),
+    (2 * 4096, 4096, 512, 4096 + 33), (2 * 4096, 4096, 256, 2100), (2 * 518, 518, 64, 777),
+    (8 * 1024, 1024, 256, 3001)])
+def test_heat_register_blocked_sweep(eq, n, width, threads, steps):
+    u0 = heat_ic(n, width + steps)
+    announce("heat register-blocked sweep", eq, n, width, threads, steps)
+    got = run(eq, pack(eq, u0), steps, 0.25, 1.0, "swept", width=width, threads=threads)
+    if eq == sw.HEAT_F64:
+        want = oracle.heat_f64(u0, steps, 0.25).reshape(1, -1)
+    else:
+        u32 = u0.astype(np.float32)
+        want = np.stack(oracle.heat_f32(u32, np.zeros_like(u32), steps, 0.25))
+    assert np.array_equal(got, want), (eq, n, width, threads, steps)
+
+
 @pytest.mark.parametrize("n,width", [(1000, 40), (1000, 250), (6, 2), (4098, 2), (3 * 2048, 1024),
                                      (2 * 8192, 8192)])
 def test_heat_f64_ragged_and_extreme_shapes(n, width):

@@ -469,3 +469,26 @@ def test_planted_binary32_recovery_fails_the_island_pin(tmp_path):
     mutant = _mutant_oracle(tmp_path)
     errs = _one_step_increment_error(mutant, _high_mach_ic(), 1e-11)
     assert min(errs) > 100 * _ISLAND_BOUND, errs
+
+
+def test_dependency_cone_is_four_cells_per_step():
+    """A cell after n Euler steps depends only on the cells within 4n of it
+    (a half step reads faces one cell away, whose limiters read pressure
+    ratios one cell further): changing any cell 4n + 1 or more cells away
+    leaves it unchanged bit for bit.  The batch tests step exact windows of
+    this width on the oracle."""
+    n_cells = 160
+    x = np.arange(n_cells) / n_cells
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * 2 * x) + 0.05 * np.cos(2 * np.pi * 9 * x)
+    u = 0.1 * np.sin(2 * np.pi * 3 * x)
+    p = 1.0 + 0.1 * np.cos(2 * np.pi * 5 * x) + 0.04 * np.sin(2 * np.pi * 11 * x)
+    q0 = np.array([rho, rho * u, p / 0.4 + 0.5 * rho * u * u])
+    for steps in (1, 2, 5):
+        base = oracle.euler_f64(q0, steps, 0.1)
+        for c in (40, 80, 121):
+            far = q0.copy()
+            lo, hi = c - 4 * steps, c + 4 * steps
+            out = np.ones(n_cells, bool)
+            out[lo:hi + 1] = False
+            far[:, out] *= 1.05
+            assert np.array_equal(oracle.euler_f64(far, steps, 0.1)[:, c], base[:, c]), (steps, c)
