@@ -84,20 +84,23 @@ NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32
 # binary32 adds three Kahan operations per component in the corrector.
 OPS_PER_UPDATE = {sw.HEAT_F64: 5, sw.HEAT_F32: 8, sw.EULER_F64: 162, sw.EULER_F32: 171,
                   sw.EULER_F64_FLAT: 162, sw.EULER_F32_FLAT: 171}
-# LDS bytes per heat cell-update of the level sweep (read, write): three
-# neighbour reads and one write; binary32 also reads and writes the
-# compensation
-LDS_BYTES_PER_UPDATE = {sw.HEAT_F64: (24, 8), sw.HEAT_F32: (16, 8)}
+# LDS bytes per heat cell-update of the register-blocked level sweep (read,
+# write): every five levels a cell's two level slots (binary32: and its
+# compensation) are read into registers and written back once
+LDS_BYTES_PER_UPDATE = {sw.HEAT_F64: (16 / 5, 16 / 5), sw.HEAT_F32: (12 / 5, 12 / 5)}
 PROFILES = os.path.join(ROOT, "profiles")
 # the persistent launch of a heat-only batch (its kernel compiles only the heat body)
-PERSISTENT_SOURCES = ["batch.hip", "batch.h", "tile_heat.h", "geom.h", "tile_job.h"]
+PERSISTENT_SOURCES = ["batch.hip", "batch.h", "tile_heat.h", "geom.h", "tile_job.h", "lanes.h",
+                      "kernels.h"]
 KERNEL_SOURCES = {
-    sw.HEAT_F64: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h"],
-    sw.HEAT_F32: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h"],
-    sw.EULER_F64: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h"],
-    sw.EULER_F32: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h"],
-    sw.EULER_F64_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h"],
-    sw.EULER_F32_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h"],
+    sw.HEAT_F64: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h", "lanes.h", "kernels.h"],
+    sw.HEAT_F32: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h", "lanes.h", "kernels.h"],
+    sw.EULER_F64: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h", "lanes.h"],
+    sw.EULER_F32: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h", "lanes.h"],
+    sw.EULER_F64_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h",
+                        "lanes.h"],
+    sw.EULER_F32_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h",
+                        "lanes.h"],
 }
 
 
@@ -471,8 +474,9 @@ def rooflines(work, eq, schedule, width, threads, ms, rate):
 # ---- one leg: swept and classic on one workload in one equation id ---------------
 
 def default_schedule(eq, work):
-    # measured on MI355X: one persistent launch wins for heat grids of 2^20
-    # cells and more (2^22: 2.12e12 against 1.98e12 cell-updates/s); on a grid
+    # measured on MI355X: one persistent launch wins or ties for heat grids
+    # of 2^20 cells and more (2^24 x 4000 steps, W = 2048: binary32 3.38e12
+    # against 3.29e12 cell-updates/s, binary64 2.83e12 either way); on a grid
     # of a few tiles the phase launches are slightly faster, and for Euler
     # the two are level or the phase launches win
     big_heat = eq in (sw.HEAT_F64, sw.HEAT_F32) and work.n >= (1 << 20)
