@@ -343,6 +343,27 @@ int sw_batch_autotune(int n_problems, sw_problem *problems, int64_t probe_steps,
  * writes up to 3 tile indices to deps and returns their count. */
 int sw_batch_item_deps(int phase, int tile, int tiles, int single_phase, int *deps);
 
+/* ---- allocation-free solve -------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * swept_solve_noalloc is swept_solve (same arguments, same result bit for
+ * bit, library-chosen width and workgroup size) with its working arrays in
+ * a static array of SW_NOALLOC_SCRATCH_BYTES bytes that the library's code
+ * object holds on each GPU until the process ends, instead of arrays the
+ * library allocates: it calls no hipMalloc, hipFree or other allocating
+ * routine.  The swept working arrays take 2 x 16 B per cell for heat
+ * binary64 (so at most 2^21 cells), 2 x 12 B for heat binary32, 2 x 56 B /
+ * 44 B for lengthened Euler and 2 x 48 B / 36 B for flattened Euler (each
+ * copy rounded up to 256 B); a larger problem is refused with SW_ERR_ARG
+ * before any HIP call.  Every call on one GPU shares that GPU's array and
+ * leaves it holding the last call's arrays: calls whose execution overlaps
+ * on the same GPU (several streams or host threads) race and corrupt each
+ * other's results; order them on one stream.  The first call on a device
+ * looks up the array's device address (hipGetSymbolAddress) and keeps it. */
+#define SW_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int swept_solve_noalloc(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
+                        void *d_state, sw_stream stream);
+
 /* Message of the last failed call on this thread ("" if none).  Valid until
  * the next library call on the same thread. */
 const char *sw_last_error(void);

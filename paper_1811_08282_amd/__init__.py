@@ -77,7 +77,7 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     i64, i32, d, vp, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
     solve_args = [i32, i64, i64, d, d, vp, vp]
-    for name in ("swept_solve", "naive_solve"):
+    for name in ("swept_solve", "naive_solve", "swept_solve_noalloc"):
         getattr(lib, name).argtypes = solve_args
         getattr(lib, name).restype = i32
     for name in ("swept_solve_ex", "naive_solve_ex"):
@@ -164,6 +164,14 @@ def swept_solve(eq, n_cells, n_steps, dt, dx, d_state, stream=None) -> int:
 
 def naive_solve(eq, n_cells, n_steps, dt, dx, d_state, stream=None) -> int:
     return load().naive_solve(eq, n_cells, n_steps, dt, dx, d_state, stream)
+
+
+# size of the static working arrays of swept_solve_noalloc (SW_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def swept_solve_noalloc(eq, n_cells, n_steps, dt, dx, d_state, stream=None) -> int:
+    return load().swept_solve_noalloc(eq, n_cells, n_steps, dt, dx, d_state, stream)
 
 
 def swept_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream=None, width=0,

@@ -471,6 +471,44 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
 
 } // namespace
 
+// ---- static working arrays of the allocation-free entry point ----------------
+//
+// One file-scope device array per GPU the library runs on (the code object
+// holds it from its load until the process ends).  In host code `scratch`
+// names a host-side stand-in, not the device address: the address is taken
+// once per device with hipGetSymbolAddress, with that device current, and
+// only that address is ever passed to kernels.
+static __device__ __align__(256) unsigned char scratch[SW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (dev is the current device).
+int scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SW_ERR_UNSUPPORTED, "device %d beyond the %d the library tracks", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(SW_ERR_HIP, "hipGetSymbolAddress of the static working arrays failed: %s",
+                        hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SW_OK;
+}
+
+} // namespace
+
 extern "C" {
 
 size_t sw_state_bytes(int eq, int64_t n_cells)
@@ -590,6 +628,35 @@ void sw_release(void)
     g_ws.clear();
     (void)hipSetDevice(cur);
     (void)hipGetLastError();
+}
+
+int swept_solve_noalloc(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
+                        void *d_state, sw_stream stream)
+{
+    int rc = check_common(eq, n_cells, n_steps, dt, dx, d_state, 4);
+    if (rc)
+        return rc;
+    // every cell's working struct is written by the phase that reads it next,
+    // so the arrays need no clearing between calls
+    const size_t need = 2 * swept_copy_bytes(eq, n_cells);
+    if (need > (size_t)SW_NOALLOC_SCRATCH_BYTES)
+        return fail(SW_ERR_ARG,
+                    "swept_solve_noalloc: %lld cells need %zu bytes of working arrays, more than "
+                    "the %zu of its static arrays (use swept_solve_ex with a workspace)",
+                    (long long)n_cells, need, (size_t)SW_NOALLOC_SCRATCH_BYTES);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SW_ERR_HIP, "hipGetDevice failed");
+    }
+    void *ws = nullptr;
+    rc = scratch_address(dev, &ws);
+    if (rc)
+        return rc;
+    sw_opts o{};
+    o.d_workspace = ws;
+    o.workspace_bytes = SW_NOALLOC_SCRATCH_BYTES;
+    return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, &o);
 }
 
 } // extern "C"

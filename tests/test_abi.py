@@ -221,3 +221,17 @@ def test_batch_phase_count_bounded_on_host():
     h = ctypes.c_void_p()
     arr = sw.problem_array(probs)
     assert sw.load().sw_batch_create(1, arr, None, ctypes.byref(h)) == sw.SW_ERR_ARG
+
+
+def test_noalloc_limits_checked_on_host():
+    """The allocation-free solve refuses, before any HIP call, a problem whose
+    working arrays exceed its static arrays, and invalid arguments."""
+    assert sw.NOALLOC_SCRATCH_BYTES == 64 * 1024 * 1024
+    # heat binary64: 2 x 16 B per cell -> 2^21 cells fit, 2^21 + 2 do not
+    rc = sw.swept_solve_noalloc(sw.HEAT_F64, (1 << 21) + 2, 5, 0.25, 1.0, FAKE, None)
+    assert rc == sw.SW_ERR_ARG and "static" in sw.last_error()
+    rc = sw.swept_solve_noalloc(sw.EULER_F64, 1 << 20, 5, 0.1, 1.0, FAKE, None)
+    assert rc == sw.SW_ERR_ARG and "static" in sw.last_error()
+    assert sw.swept_solve_noalloc(9, 1024, 5, 0.25, 1.0, FAKE, None) == sw.SW_ERR_ARG
+    assert sw.swept_solve_noalloc(sw.HEAT_F64, 1024, -1, 0.25, 1.0, FAKE, None) == sw.SW_ERR_ARG
+    assert sw.swept_solve_noalloc(sw.HEAT_F64, 1024, 5, 0.25, 1.0, None, None) == sw.SW_ERR_ARG
