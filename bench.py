@@ -578,6 +578,51 @@ def width_sweep(torch, work, eq, widths, reps, naive_reps):
             "naive": {"value": updates / (nms * 1e-3), "ms_per_solve": nms, "reps": naive_reps}}
 
 
+def wf_sweep(torch, work, eq, tiles_per_thread, host_threads, reps):
+    """The swept solve shared with host threads (sw_opts.work_factor), against
+    the GPU alone, on one workload; each host thread takes k tiles for k in
+    tiles_per_thread (work factor T/k - P for T tiles, P threads)."""
+    import statistics
+    state0 = pack_state(eq, wl.initial_state(work))
+    width = sw.sw_default_width(eq, work.n)
+    tiles = work.n // width
+    updates = work.n * work.steps
+    pristine = torch.from_numpy(np.ascontiguousarray(state0)).cuda()
+    dev = pristine.clone()
+
+    def timed(wf):
+        times = []
+        for _ in range(reps + 1):
+            dev.copy_(pristine)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sw.solve(eq, dev, work.steps, work.dt, work.dx, method="swept", width=width,
+                     work_factor=wf, host_threads=host_threads if wf else 0)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        return statistics.median(times[1:])
+
+    rows = []
+    ms = timed(0)
+    rows.append({"work_factor": 0, "host_tiles": 0, "gpu_tiles": tiles, "ms_per_solve": ms,
+                 "value": updates / (ms * 1e-3)})
+    log(f"[bench] wf sweep {leg_label(work, eq)}: GPU alone {ms:.1f} ms")
+    for k in tiles_per_thread:
+        wf = tiles // k - host_threads
+        if wf < 1:
+            continue
+        kt = tiles // (wf + host_threads)
+        ms = timed(wf)
+        row = {"work_factor": wf, "tiles_per_host_thread": kt, "host_tiles": host_threads * kt,
+               "gpu_tiles": tiles - host_threads * kt,
+               "gpu_over_host_thread": (tiles - host_threads * kt) / kt,
+               "ms_per_solve": ms, "value": updates / (ms * 1e-3)}
+        log(f"[bench] wf sweep: {json.dumps(row)}")
+        rows.append(row)
+    return {"workload": leg_label(work, eq), "width": width, "tiles": tiles,
+            "host_threads": host_threads, "reps": reps, "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -599,9 +644,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-naive", action="store_true", help="skip the classic-path timing")
     ap.add_argument("--no-verify", action="store_true", help="skip the sampled oracle checks")
-    ap.add_argument("--sweep", default=None, choices=["c2", "c1"],
+    ap.add_argument("--sweep", default=None, choices=["c2", "c1", "wf"],
                     help="width sweep of the 2^22-cell heat workload (c2, widths 64 to the LDS "
-                         "limit) or the 1024-cell one at W = 64 (c1)")
+                         "limit), the 1024-cell one at W = 64 (c1), or the GPU work factor of a "
+                         "solve shared with host threads (wf: heat 2^22 cells, Euler 2^24)")
+    ap.add_argument("--host-threads", type=int, default=8,
+                    help="host threads of the work-factor sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -628,6 +676,14 @@ def main() -> int:
         return 0
     sw.load()
 
+    if args.sweep == "wf":
+        res = {"metric": "cell-updates/s",
+               "sweeps": [wf_sweep(torch, wl.HEAT_LARGE, sw.HEAT_F64, [1, 2, 4], args.host_threads,
+                                   max(args.steps, 1)),
+                          wf_sweep(torch, wl.EULER_PREC, sw.EULER_F64, [1, 2, 4, 8],
+                                   args.host_threads, 1)]}
+        print(json.dumps(res), flush=True)
+        return 0
     if args.sweep:
         if args.sweep == "c2":
             work, eq = wl.HEAT_LARGE, sw.HEAT_F64

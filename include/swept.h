@@ -106,12 +106,31 @@ typedef void *sw_stream;
  *                     sw_workspace_bytes() long, 256-byte aligned), or NULL
  *                     for the library's cached arrays.  Required when the
  *                     stream is being captured into a graph.
- *   workspace_bytes : size of d_workspace.                                  */
+ *   workspace_bytes : size of d_workspace.
+ *   work_factor     : swept only.  0 = the GPU takes every tile.  WF >= 1
+ *                     shares the grid with host threads as the paper's GPU
+ *                     work factor (Sec. 4.2, Eq. 1): each of the
+ *                     host_threads threads takes k = floor(T / (WF + P))
+ *                     consecutive tiles (T = n_cells / W tiles, P host
+ *                     threads) and the GPU the remaining T - P k, at least
+ *                     WF times a thread's share.  Host threads advance their
+ *                     tiles with host-compiled copies of the kernels' cell
+ *                     arithmetic (same results bit for bit); once per phase
+ *                     the two sides exchange the W/2 + R seam structs they
+ *                     need from each other through pinned host memory.  The
+ *                     call then runs on the calling thread until the solve
+ *                     is complete (it synchronises `stream`); it cannot be
+ *                     captured (SW_ERR_CAPTURE) and needs at least two
+ *                     phases (one heat step runs on the GPU alone).
+ *                     SW_ERR_ARG when k would be 0.
+ *   host_threads    : host threads of a shared solve, 0 = 8.               */
 typedef struct {
     int width;
     int threads;
     void *d_workspace;
     size_t workspace_bytes;
+    int work_factor;
+    int host_threads;
 } sw_opts;
 
 /* Bytes of the state buffer for `eq` and n_cells (0 for an invalid eq). */

@@ -39,7 +39,8 @@ class SweptError(RuntimeError):
 
 class sw_opts(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int), ("threads", ctypes.c_int),
-                ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("d_workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("work_factor", ctypes.c_int), ("host_threads", ctypes.c_int)]
 
 
 class sw_problem(ctypes.Structure):
@@ -147,12 +148,14 @@ def last_error() -> str:
 
 
 def _opts(width: int = 0, workspace: int | None = None, workspace_bytes: int = 0,
-          threads: int = 0):
+          threads: int = 0, work_factor: int = 0, host_threads: int = 0):
     o = sw_opts()
     o.width = int(width)
     o.threads = int(threads)
     o.d_workspace = workspace
     o.workspace_bytes = int(workspace_bytes)
+    o.work_factor = int(work_factor)
+    o.host_threads = int(host_threads)
     return o
 
 
@@ -175,8 +178,9 @@ def swept_solve_noalloc(eq, n_cells, n_steps, dt, dx, d_state, stream=None) -> i
 
 
 def swept_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream=None, width=0,
-                   workspace=None, workspace_bytes=0, threads=0) -> int:
-    o = _opts(width, workspace, workspace_bytes, threads)
+                   workspace=None, workspace_bytes=0, threads=0, work_factor=0,
+                   host_threads=0) -> int:
+    o = _opts(width, workspace, workspace_bytes, threads, work_factor, host_threads)
     return load().swept_solve_ex(eq, n_cells, n_steps, dt, dx, d_state, stream, ctypes.byref(o))
 
 
@@ -385,11 +389,14 @@ def state_rows(eq: int) -> int:
 
 
 def solve(eq: int, state, n_steps: int, dt: float, dx: float, method: str = "swept",
-          width: int = 0, workspace=None, stream=None, threads: int = 0) -> None:
+          width: int = 0, workspace=None, stream=None, threads: int = 0, work_factor: int = 0,
+          host_threads: int = 0) -> None:
     """Advance a torch device tensor of shape (rows, n_cells) in place.
 
     ``rows`` is :func:`state_rows`; the dtype is float64 for *_F64 and float32
     for *_F32.  Runs on ``stream`` (default: torch's current stream).
+    ``work_factor`` > 0 shares the swept solve with ``host_threads`` host
+    threads (sw_opts.work_factor); the call then returns when it is done.
     """
     import torch
     if not state.is_cuda or not state.is_contiguous():
@@ -403,7 +410,7 @@ def solve(eq: int, state, n_steps: int, dt: float, dx: float, method: str = "swe
     ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     if method == "swept":
         rc = swept_solve_ex(eq, n, n_steps, dt, dx, state.data_ptr(), handle, width, ws_ptr,
-                            ws_bytes, threads)
+                            ws_bytes, threads, work_factor, host_threads)
     elif method == "naive":
         rc = naive_solve_ex(eq, n, n_steps, dt, dx, state.data_ptr(), handle, ws_ptr, ws_bytes)
     else:

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswept.so")
-SOURCES = ["api.cpp", "tune_batch.cpp", "heat.hip", "euler.hip", "euler_flat.hip", "batch.hip"]
+SOURCES = ["api.cpp", "tune_batch.cpp", "host_share.cpp", "heat.hip", "euler.hip", "euler_flat.hip",
+           "batch.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -269,6 +269,39 @@ int launched(hipError_t e, const char *what)
     return SW_OK;
 }
 
+hipError_t swept_phase_launch(int eq, const sw::PhaseLaunch &p, void *state, const void *in,
+                              void *out, double dt, double dx, hipStream_t s)
+{
+    const double r64 = dt / (dx * dx);
+    const double lam64 = dt / dx;
+    hipError_t e = hipSuccess;
+    switch (eq) {
+    case SW_HEAT_F64:
+        e = sw::heat_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out, r64, s);
+        break;
+    case SW_HEAT_F32:
+        e = sw::heat_f32_swept_phase(p, (float *)state, (const float *)in, (float *)out,
+                                     (float)r64, s);
+        break;
+    case SW_EULER_F64:
+        e = sw::euler_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out,
+                                      lam64, s);
+        break;
+    case SW_EULER_F32:
+        e = sw::euler_f32_swept_phase(p, (float *)state, in, out, (float)lam64, s);
+        break;
+    case SW_EULER_F64_FLAT:
+        e = sw::flat_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out, lam64,
+                                     s);
+        break;
+    default:
+        e = sw::flat_f32_swept_phase(p, (float *)state, (const float *)in, (float *)out,
+                                     (float)lam64, s);
+        break;
+    }
+    return e;
+}
+
 } // namespace host
 } // namespace sw
 
@@ -288,14 +321,13 @@ int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
     const size_t copy = swept_copy_bytes(eq, n);
     char *ws_a = (char *)ws;
     char *ws_b = ws_a + copy;
-    const double r64 = dt / (dx * dx);
-    const double lam64 = dt / dx;
     for (int64_t k = 1; k <= phases; ++k) {
         const sw::PhaseRange pr = sw::phase_range(k, final_level, half, rad);
         sw::PhaseLaunch p;
         p.n = n;
         p.w = w;
         p.offset = pr.offset;
+        p.tiles = n / w;
         p.base = pr.base;
         p.j_first = pr.j_first;
         p.j_last = pr.j_last;
@@ -307,32 +339,7 @@ int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
         p.last = (k == phases) && phases > 1;
         char *in = (k % 2 == 0) ? ws_a : ws_b;
         char *out = (k % 2 == 1) ? ws_a : ws_b;
-        hipError_t e = hipSuccess;
-        switch (eq) {
-        case SW_HEAT_F64:
-            e = sw::heat_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out,
-                                         r64, s);
-            break;
-        case SW_HEAT_F32:
-            e = sw::heat_f32_swept_phase(p, (float *)state, (const float *)in, (float *)out,
-                                         (float)r64, s);
-            break;
-        case SW_EULER_F64:
-            e = sw::euler_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out,
-                                          lam64, s);
-            break;
-        case SW_EULER_F32:
-            e = sw::euler_f32_swept_phase(p, (float *)state, in, out, (float)lam64, s);
-            break;
-        case SW_EULER_F64_FLAT:
-            e = sw::flat_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out,
-                                         lam64, s);
-            break;
-        default:
-            e = sw::flat_f32_swept_phase(p, (float *)state, (const float *)in, (float *)out,
-                                         (float)lam64, s);
-            break;
-        }
+        const hipError_t e = swept_phase_launch(eq, p, state, in, out, dt, dx, s);
         if (e != hipSuccess)
             return launched(e, "swept phase launch");
     }
@@ -438,6 +445,20 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
         return fail(SW_ERR_ARG, "threads must be 0, 64, 128, 256 or 512");
     if (o && o->d_workspace && ((uintptr_t)o->d_workspace & 255) != 0)
         return fail(SW_ERR_ARG, "workspace must be 256-byte aligned");
+    if (o && (o->work_factor < 0 || o->host_threads < 0 || o->host_threads > kMaxHostThreads))
+        return fail(SW_ERR_ARG, "work_factor must be >= 0 and host_threads in [0, %d]",
+                    kMaxHostThreads);
+    if (o && o->work_factor > 0) {
+        if (method != SW_METHOD_SWEPT)
+            return fail(SW_ERR_ARG, "work_factor applies to the swept method only");
+        const int64_t tiles = n / w;
+        const int p = o->host_threads ? o->host_threads : kDefaultHostThreads;
+        if (tiles / ((int64_t)o->work_factor + p) < 1)
+            return fail(SW_ERR_ARG,
+                        "work_factor %d with %d host threads leaves no tile for the host (%lld "
+                        "tiles of %d cells)",
+                        o->work_factor, p, (long long)tiles, w);
+    }
     const int threads = (o && o->threads) ? o->threads
                         : (tuned_threads ? tuned_threads : default_threads(eq, w));
     // a launch holds at most 2^32 - 1 work-items: one workgroup per tile in
@@ -464,8 +485,13 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
     rc = get_workspace(dev, s, need, o, &ws);
     if (rc)
         return rc;
-    rc = (method == SW_METHOD_SWEPT) ? run_swept(eq, n, steps, dt, dx, state, s, w, threads, ws)
-                                     : run_naive(eq, n, steps, dt, dx, state, s, ws);
+    if (method == SW_METHOD_SWEPT && o && o->work_factor > 0 &&
+        sw::phase_count(steps * substeps(eq), w / (2 * radius(eq))) >= 2)
+        rc = run_swept_shared(eq, n, steps, dt, dx, state, s, w, threads, ws, o->work_factor,
+                              o->host_threads);
+    else
+        rc = (method == SW_METHOD_SWEPT) ? run_swept(eq, n, steps, dt, dx, state, s, w, threads, ws)
+                                         : run_naive(eq, n, steps, dt, dx, state, s, ws);
     return rc ? rc : ok();
 }
 
@@ -615,6 +641,7 @@ const char *sw_last_error(void) { return sw::host::last_error(); }
 
 void sw_release(void)
 {
+    release_host_arrays();
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     int cur = 0;
     (void)hipGetDevice(&cur);

@@ -152,7 +152,7 @@ hipError_t euler_f64_swept_phase(const PhaseLaunch &p, double *state, const doub
                                  double *ws_out, double lam, hipStream_t s)
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellEulerF64;
-    const dim3 g = dim3((unsigned)(p.n / p.w));
+    const dim3 g = dim3((unsigned)p.tiles);
     if (p.threads == 512) {
         switch (p.w) {  // the default launch of Euler tiles of 1024 cells and more
         case 1024: return launch_kernel(k_euler_f64_phase<512, 1024>, g, 512, lds, s,
@@ -200,7 +200,7 @@ hipError_t euler_f32_swept_phase(const PhaseLaunch &p, float *state, const void 
                                  void *ws_out, float lam, hipStream_t s)
 {
     const size_t lds = (size_t)(p.w + 2) * kLdsPerCellEulerF32;
-    const dim3 g = dim3((unsigned)(p.n / p.w));
+    const dim3 g = dim3((unsigned)p.tiles);
     if (p.threads == 512) {
         switch (p.w) {  // the default launch of Euler tiles of 1024 cells and more
         case 1024: return launch_kernel(k_euler_f32_phase<512, 1024>, g, 512, lds, s,

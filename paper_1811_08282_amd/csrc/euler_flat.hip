@@ -136,7 +136,7 @@ hipError_t flat_f64_swept_phase(const PhaseLaunch &p, double *state, const doubl
                                 double *ws_out, double lam, hipStream_t s)
 {
     const size_t lds = (size_t)(p.w + 2 * kFlatRadius) * kLdsPerCellFlatF64;
-    const dim3 g = dim3((unsigned)(p.n / p.w));
+    const dim3 g = dim3((unsigned)p.tiles);
     if (p.threads == 512) {
         switch (p.w) {  // the default launch of Euler tiles of 1024 cells and more
         case 1024: return launch_kernel(k_flat_f64_phase<512, 1024>, g, 512, lds, s,
@@ -174,7 +174,7 @@ hipError_t flat_f32_swept_phase(const PhaseLaunch &p, float *state, const float 
                                 float *ws_out, float lam, hipStream_t s)
 {
     const size_t lds = (size_t)(p.w + 2 * kFlatRadius) * kLdsPerCellFlatF32;
-    const dim3 g = dim3((unsigned)(p.n / p.w));
+    const dim3 g = dim3((unsigned)p.tiles);
     if (p.threads == 512) {
         switch (p.w) {  // the default launch of Euler tiles of 1024 cells and more
         case 1024: return launch_kernel(k_flat_f32_phase<512, 1024>, g, 512, lds, s,

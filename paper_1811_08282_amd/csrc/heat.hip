@@ -122,7 +122,7 @@ hipError_t heat_f64_swept_phase(const PhaseLaunch &p, double *state, const doubl
 {
     const size_t lds = (size_t)lds_tile_cells(true, p.w, 1) * kLdsPerCellHeatF64;
     return launch_by_threads(p.threads, k_heat_f64_phase<64>, k_heat_f64_phase<128>,
-                             k_heat_f64_phase<256>, k_heat_f64_phase<512>, dim3((unsigned)(p.n / p.w)), lds, s, state,
+                             k_heat_f64_phase<256>, k_heat_f64_phase<512>, dim3((unsigned)p.tiles), lds, s, state,
                              ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, r,
                              (int)p.first, (int)p.last);
 }
@@ -146,7 +146,7 @@ hipError_t heat_f32_swept_phase(const PhaseLaunch &p, float *state, const float 
 {
     const size_t lds = (size_t)lds_tile_cells(true, p.w, 1) * kLdsPerCellHeatF32;
     return launch_by_threads(p.threads, k_heat_f32_phase<64>, k_heat_f32_phase<128>,
-                             k_heat_f32_phase<256>, k_heat_f32_phase<512>, dim3((unsigned)(p.n / p.w)), lds, s, state,
+                             k_heat_f32_phase<256>, k_heat_f32_phase<512>, dim3((unsigned)p.tiles), lds, s, state,
                              ws_in, ws_out, p.n, p.w, p.offset, p.base, p.j_first, p.j_last, r,
                              (int)p.first, (int)p.last);
 }

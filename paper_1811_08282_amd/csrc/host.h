@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../include/swept.h"
+#include "kernels.h"
 
 namespace sw {
 namespace host {
@@ -36,6 +37,25 @@ int check_common(int eq, int64_t n, int64_t steps, double dt, double dx, const v
                  int64_t min_cells);
 int check_device_pointer(const void *p, int *dev_out);
 int launched(hipError_t e, const char *what);
+
+size_t state_bytes(int eq, int64_t n);
+
+// host threads of a shared solve when the caller gives none, and the most
+constexpr int kDefaultHostThreads = 8;
+constexpr int kMaxHostThreads = 256;
+
+// one swept phase launch of equation id eq (p.tiles tiles from p.offset)
+hipError_t swept_phase_launch(int eq, const sw::PhaseLaunch &p, void *state, const void *in,
+                              void *out, double dt, double dx, hipStream_t s);
+
+// the swept solve shared between the GPU and host threads (sw_opts.work_factor);
+// ws: the device working arrays; synchronises the stream before returning
+int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, void *state,
+                     hipStream_t s, int w, int threads, void *ws, int work_factor,
+                     int host_threads);
+
+// free the pinned host arrays of shared solves
+void release_host_arrays();
 
 // width of a swept solve when the caller gives none: the tuned width of
 // (device, eq, n) if sw_autotune recorded one, else default_width; threads

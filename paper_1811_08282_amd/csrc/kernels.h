@@ -43,7 +43,9 @@ inline int lds_tile_cells(bool heat, int w, int radius)
 struct PhaseLaunch {
     int64_t n;        // cells
     int w;            // tile width
-    int64_t offset;   // first cell of tile 0 (0 or w/2)
+    int64_t offset;   // first cell of the launch's first tile (the tiling's offset, 0 or
+                      // w/2, plus w times the index of that tile)
+    int64_t tiles;    // tiles (workgroups) of the launch: n / w, or the GPU's share
     int64_t base;     // (k - 1) * w/2
     int j_first, j_last;
     bool first;       // reads the caller's state (level 0 of this call)

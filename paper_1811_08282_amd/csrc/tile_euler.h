@@ -40,14 +40,14 @@ namespace sw {
 constexpr double kGamma = 1.4;
 constexpr double kGm1 = 0.4;
 
-__device__ __forceinline__ double limiter(double q)
+__host__ __device__ __forceinline__ double limiter(double q)
 {
     if (q > 0.0)
         return q < 1.0 ? q : 1.0;
     return 0.0;
 }
 
-__device__ __forceinline__ double ratio(double pm, double pc, double pp)
+__host__ __device__ __forceinline__ double ratio(double pm, double pc, double pp)
 {
     return (pp - pc) / (pc - pm);
 }
@@ -56,13 +56,13 @@ constexpr int kFaceLanes = 63;  // cells a wave updates per pass (lane 63: face 
 
 // ---- binary64 ----------------------------------------------------------------
 
-__device__ __forceinline__ double pressure64(double rho, double m, double e)
+__host__ __device__ __forceinline__ double pressure64(double rho, double m, double e)
 {
     const double u = m / rho;
     return kGm1 * (e - 0.5 * (m * u));
 }
 
-__device__ __forceinline__ void face64(double a0, double a1, double a2, double b0, double b1,
+__host__ __device__ __forceinline__ void face64(double a0, double a1, double a2, double b0, double b1,
                                        double b2, double pra, double prb, double &f0, double &f1,
                                        double &f2)
 {
@@ -86,7 +86,7 @@ __device__ __forceinline__ void face64(double a0, double a1, double a2, double b
 }
 
 // top level of LDS cell i when a phase starts (halos: the previous peak)
-__device__ __forceinline__ int64_t entry_level(const TileJob &jb, int i, int w)
+__host__ __device__ __forceinline__ int64_t entry_level(const TileJob &jb, int i, int w)
 {
     if (jb.first)
         return 0;
@@ -190,14 +190,14 @@ __device__ __forceinline__ void euler_f64_tile(const TileJob &jb, double *lds)
 
 // ---- binary32 with binary64 islands ------------------------------------------
 
-__device__ __forceinline__ double pressure32(float rho, float m, float e)
+__host__ __device__ __forceinline__ double pressure32(float rho, float m, float e)
 {
     const double dr = (double)rho, dm = (double)m, de = (double)e;
     const double u = dm / dr;
     return kGm1 * (de - 0.5 * (dm * u));
 }
 
-__device__ __forceinline__ void face32(float a0, float a1, float a2, float b0, float b1, float b2,
+__host__ __device__ __forceinline__ void face32(float a0, float a1, float a2, float b0, float b1, float b2,
                                        double pra, double prb, float &f0, float &f1, float &f2)
 {
     const float hl = 0.5f * (float)limiter(1.0 / pra);
@@ -222,7 +222,7 @@ __device__ __forceinline__ void face32(float a0, float a1, float a2, float b0, f
     f2 = 0.5f * ((l2 + pl) * vl + (r2 + pr) * vr) - hs * (r2 - l2);
 }
 
-__device__ __forceinline__ float kahan_add(float q, float d, float &c)
+__host__ __device__ __forceinline__ float kahan_add(float q, float d, float &c)
 {
     const float y = d - c;
     const float t = q + y;

@@ -42,12 +42,12 @@
 
 namespace sw {
 
-__device__ __forceinline__ double heat_update(double l, double c, double r_, double r)
+__host__ __device__ __forceinline__ double heat_update(double l, double c, double r_, double r)
 {
     return c + r * ((r_ - c) + (l - c));
 }
 
-__device__ __forceinline__ float heat_update_kahan(float l, float c, float rr, float r, float &comp)
+__host__ __device__ __forceinline__ float heat_update_kahan(float l, float c, float rr, float r, float &comp)
 {
     const float d = r * ((rr - c) + (l - c));
     const float y = d - comp;

@@ -26,7 +26,7 @@ struct TileJob {
     int64_t final_level; // F when this phase is cut flat at F, else its top level
 };
 
-__device__ __forceinline__ int64_t wrap_cell(int64_t g, int64_t n)
+__host__ __device__ __forceinline__ int64_t wrap_cell(int64_t g, int64_t n)
 {
     if (g < 0)
         return g + n;

@@ -138,7 +138,7 @@ def test_python_binding_names_match_c_abi():
                  "sw_default_threads",
                  "sw_phase_count", "sw_phase_info", "sw_phase_interval", "sw_release"):
         assert callable(getattr(sw, name))
-    assert ctypes.sizeof(sw.sw_opts) == 24
+    assert ctypes.sizeof(sw.sw_opts) == 32
 
 
 def test_launch_work_item_limit_rejected_on_host():
@@ -235,3 +235,20 @@ def test_noalloc_limits_checked_on_host():
     assert sw.swept_solve_noalloc(9, 1024, 5, 0.25, 1.0, FAKE, None) == sw.SW_ERR_ARG
     assert sw.swept_solve_noalloc(sw.HEAT_F64, 1024, -1, 0.25, 1.0, FAKE, None) == sw.SW_ERR_ARG
     assert sw.swept_solve_noalloc(sw.HEAT_F64, 1024, 5, 0.25, 1.0, None, None) == sw.SW_ERR_ARG
+
+
+def test_work_factor_checked_on_host():
+    """A shared solve is refused on the host when the work factor leaves the
+    host no tile, for the classic method, and for negative values."""
+    # 1024 cells in tiles of 64: 16 tiles; WF 1 with 8 threads: 16 // 9 = 1 tile each
+    rc = sw.swept_solve_ex(sw.HEAT_F64, 1024, 5, 0.25, 1.0, FAKE, None, width=64, work_factor=9,
+                           host_threads=8)
+    assert rc == sw.SW_ERR_ARG and "no tile" in sw.last_error()
+    rc = sw.swept_solve_ex(sw.HEAT_F64, 1024, 5, 0.25, 1.0, FAKE, None, width=64, work_factor=-1)
+    assert rc == sw.SW_ERR_ARG
+    rc = sw.swept_solve_ex(sw.HEAT_F64, 1024, 5, 0.25, 1.0, FAKE, None, width=64,
+                           host_threads=100000)
+    assert rc == sw.SW_ERR_ARG
+    o = sw._opts(work_factor=2)
+    rc = sw.load().naive_solve_ex(sw.HEAT_F64, 1024, 5, 0.25, 1.0, FAKE, None, ctypes.byref(o))
+    assert rc == sw.SW_ERR_ARG and "swept" in sw.last_error()
