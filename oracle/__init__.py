@@ -50,8 +50,9 @@ def _load():
     lib.oracle_euler_f64.argtypes = [vp, vp, vp, i64, i64, d, i32]
     lib.oracle_euler_f32.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, f, i32]
     lib.oracle_threads_used.argtypes = [i32]
+    lib.oracle_ks_f64.argtypes = [vp, i64, i64, d, d, d, i32]
     for fn in (lib.oracle_heat_f64, lib.oracle_heat_f32, lib.oracle_euler_f64,
-               lib.oracle_euler_f32, lib.oracle_threads_used):
+               lib.oracle_euler_f32, lib.oracle_threads_used, lib.oracle_ks_f64):
         fn.restype = i32
     _lib = lib
     return lib
@@ -110,3 +111,20 @@ def euler_f32(q0, c0, steps: int, lam: float, threads: int = 0):
     if rc:
         raise ValueError(f"oracle_euler_f32 failed ({rc})")
     return q, c
+
+
+def ks_coefficients(dt: float, dx: float):
+    """(a, b, c) = (dt / (2 dx), dt / dx^2, dt / dx^4), evaluated in binary64 in
+    this form; the Kuramoto-Sivashinsky scheme takes them as given."""
+    return dt / (2.0 * dx), dt / (dx * dx), dt / ((dx * dx) * (dx * dx))
+
+
+def ks_f64(u0, steps: int, dt: float, dx: float, threads: int = 0) -> np.ndarray:
+    """Kuramoto-Sivashinsky equation, forward Euler / central differences,
+    binary64, periodic; returns the state after ``steps``."""
+    u = np.array(u0, dtype=np.float64, copy=True, order="C")
+    a, b, c = ks_coefficients(dt, dx)
+    rc = _load().oracle_ks_f64(_ptr(u), u.size, int(steps), a, b, c, int(threads))
+    if rc:
+        raise ValueError(f"oracle_ks_f64 failed ({rc})")
+    return u

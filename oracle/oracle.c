@@ -19,6 +19,9 @@
  *           organised as four three-point sub-steps per time step with a
  *           stored pressure ratio (the "lengthening" layout, Sec. 4.3,
  *           Fig. 2b): Pr(Q0) -> predictor -> Pr(Q1) -> corrector.
+ *   ks    : the Kuramoto-Sivashinsky equation, which the paper names (Sec. 2)
+ *           among the equations the swept rule has been applied to; forward
+ *           Euler in time, central differences, a five-point stencil.
  *
  * The paper defers the exact scheme equations to an earlier article; the
  * reading used here (textbook FTCS; pressure-ratio minmod reconstruction,
@@ -376,5 +379,57 @@ int oracle_euler_f32(float *rho, float *mom, float *ene, float *crho, float *cmo
     }
     free(fb);
     free(db);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Kuramoto-Sivashinsky equation  u_t + u u_x + u_xx + u_xxxx = 0
+ * (named in Sec. 2 among the equations the swept rule has been applied
+ * to; the paper gives no scheme).  Reading: forward Euler in time, the
+ * advection in conservative form with a central difference of the flux
+ * u^2/2, the second derivative as the difference form of the heat scheme
+ * and the fourth derivative as the same second difference applied to the
+ * second differences.  Per time step, each stage over every cell before
+ * the next:
+ *   s_i  = (u_{i+1} - u_i) + (u_{i-1} - u_i)
+ *   f_i  = 0.5 * (u_i * u_i)
+ *   q_i  = (s_{i+1} - s_i) + (s_{i-1} - s_i)
+ *   u_i <- u_i - ((a * (f_{i+1} - f_{i-1}) + b * s_i) + c * q_i)
+ * with a = dt / (2 dx), b = dt / dx^2, c = dt / dx^4 (passed in).
+ * ---------------------------------------------------------------------- */
+int oracle_ks_f64(double *u, int64_t n, int64_t steps, double a, double b, double c,
+                  int threads)
+{
+    if (n < 5 || steps < 0 || !u)
+        return 1;
+    double *s2 = (double *)malloc((size_t)n * sizeof(double));
+    double *fl = (double *)malloc((size_t)n * sizeof(double));
+    double *q4 = (double *)malloc((size_t)n * sizeof(double));
+    if (!s2 || !fl || !q4) {
+        free(s2);
+        free(fl);
+        free(q4);
+        return 4;
+    }
+    set_threads(threads);
+    for (int64_t st = 0; st < steps; ++st) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            const double mid = u[i];
+            s2[i] = (u[wrap(i + 1, n)] - mid) + (u[wrap(i - 1, n)] - mid);
+            fl[i] = 0.5 * (mid * mid);
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            const double mid = s2[i];
+            q4[i] = (s2[wrap(i + 1, n)] - mid) + (s2[wrap(i - 1, n)] - mid);
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            u[i] = u[i] - ((a * (fl[wrap(i + 1, n)] - fl[wrap(i - 1, n)]) + b * s2[i]) + c * q4[i]);
+    }
+    free(s2);
+    free(fl);
+    free(q4);
     return 0;
 }
