@@ -68,18 +68,19 @@ WORKLOADS = {
     "euler_f64_flat_large": (wl.EULER_LARGE, sw.EULER_F64_FLAT),
     "euler_f32_flat_prec": (wl.EULER_PREC, sw.EULER_F32_FLAT),
     "euler_f64_flat_prec": (wl.EULER_PREC, sw.EULER_F64_FLAT),
+    "ks_f64_prec": (wl.KS_PREC, sw.KS_F64),
 }
 # the default run: the 2^24-cell configuration in every equation id; the first
 # leg is the headline value
 DEFAULT_LEGS = ["heat_f64_prec", "heat_f32_prec", "euler_f64_prec", "euler_f32_prec",
-                "euler_f64_flat_prec", "euler_f32_flat_prec"]
+                "euler_f64_flat_prec", "euler_f32_flat_prec", "ks_f64_prec"]
 
 # algorithmic bytes of the swept working struct per cell (read + write per phase)
 STRUCT_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 12, sw.EULER_F64: 56, sw.EULER_F32: 44,
-                sw.EULER_F64_FLAT: 48, sw.EULER_F32_FLAT: 36}
+                sw.EULER_F64_FLAT: 48, sw.EULER_F32_FLAT: 36, sw.KS_F64: 16}
 # algorithmic HBM bytes per cell-update of the classic path
 NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32: 140,
-               sw.EULER_F64_FLAT: 120, sw.EULER_F32_FLAT: 84}
+               sw.EULER_F64_FLAT: 120, sw.EULER_F32_FLAT: 84, sw.KS_F64: 16}
 # arithmetic operations per cell-update (one cell, one time step), counted from
 # the scheme: every add, subtract, multiply, divide, square root, comparison and
 # absolute value is one operation.  Heat: two differences, their sum, the
@@ -88,8 +89,10 @@ NAIVE_BYTES = {sw.HEAT_F64: 16, sw.HEAT_F32: 16, sw.EULER_F64: 200, sw.EULER_F32
 # ratio, two limiters, reconstruction, two primitive recoveries, two sound
 # speeds, the two physical fluxes, the Rusanov dissipation), update 9;
 # binary32 adds three Kahan operations per component in the corrector.
+# Kuramoto-Sivashinsky: the second difference 3, the flux 2, the fourth
+# difference 3, the update 7 (each stage once per cell).
 OPS_PER_UPDATE = {sw.HEAT_F64: 5, sw.HEAT_F32: 8, sw.EULER_F64: 162, sw.EULER_F32: 171,
-                  sw.EULER_F64_FLAT: 162, sw.EULER_F32_FLAT: 171}
+                  sw.EULER_F64_FLAT: 162, sw.EULER_F32_FLAT: 171, sw.KS_F64: 15}
 # LDS bytes per heat cell-update of the register-blocked level sweep (read,
 # write): every five levels a cell's two level slots (binary32: and its
 # compensation) are read into registers and written back once
@@ -107,6 +110,7 @@ KERNEL_SOURCES = {
                         "lanes.h"],
     sw.EULER_F32_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h",
                         "lanes.h"],
+    sw.KS_F64: ["tile_ks.h", "ks.hip", "geom.h", "tile_job.h", "kernels.h"],
 }
 
 
@@ -151,7 +155,7 @@ def log(*a):
 
 def pack_state(eq, q):
     q = np.asarray(q, np.float64)
-    if eq == sw.HEAT_F64:
+    if eq in (sw.HEAT_F64, sw.KS_F64):
         return q.reshape(1, -1)
     if eq == sw.HEAT_F32:
         return np.stack([q.astype(np.float32), np.zeros(q.shape, np.float32)])
@@ -203,6 +207,18 @@ def verify_sample(work, eq, gpu):
     q0 = wl.initial_state(work)
     out = {"reference": "oracle"}
     cached = _oracle_cached
+    if eq == sw.KS_F64:
+        span, reach = 16, 2 * work.steps + 2
+        starts = [0, work.n // 3 + 5, work.n - 7, 12345 % work.n]
+        ref = cached((work.name, "ks"), lambda: [
+            oracle.ks_f64(q0[np.arange(s0 - reach, s0 + span + reach) % work.n], work.steps,
+                          work.dt, work.dx)[reach: reach + span] for s0 in starts])
+        got = np.concatenate([gpu[0][np.arange(s0, s0 + span) % work.n] for s0 in starts])
+        want = np.concatenate(ref)
+        out["bit_exact"] = bool(np.array_equal(got, want))
+        out["max_abs_diff"] = float(np.max(np.abs(got - want)))
+        out["sample"] = f"{len(starts)} windows of {span} cells (exact dependency cones, radius 2)"
+        return out
     if eq in (sw.HEAT_F64, sw.HEAT_F32):
         r = work.dt / (work.dx * work.dx)
         span = 16
@@ -266,7 +282,13 @@ def cpu_baseline(work, eq, budget_s):
     q = wl.initial_state(work)
     chunk = 20
     done, t_used = 0, 0.0
-    if eq in (sw.HEAT_F64, sw.HEAT_F32):
+    if eq == sw.KS_F64:
+        arg = None
+        cells = work.n
+
+        def run(s, k, a):
+            return oracle.ks_f64(s, k, work.dt, work.dx)
+    elif eq in (sw.HEAT_F64, sw.HEAT_F32):
         arg = work.dt / (work.dx * work.dx)
         cells = work.n
         if eq == sw.HEAT_F64:
@@ -294,7 +316,7 @@ def cpu_baseline(work, eq, budget_s):
         t_used += time.perf_counter() - t0
         done += chunk
     work_units = cells * done
-    if eq not in (sw.HEAT_F64, sw.HEAT_F32) and done >= work.steps and t_used < budget_s:
+    if work.eq == "euler" and done >= work.steps and t_used < budget_s:
         # one tile finished inside the budget: step a block of further whole
         # tiles (still periodic with the tile) over all steps, once
         more = min(int((budget_s - t_used) / t_used), work.n // work.tile - 1)

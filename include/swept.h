@@ -21,6 +21,14 @@
  *           (SW_EULER_*_FLAT), two five-point sub-steps -- predictor,
  *           corrector, each recomputing the ratio -- on a struct of Q0, Q1.
  *           Both leave bit-identical states after every time step.
+ *   ks    : Kuramoto-Sivashinsky u_t + u u_x + u_xx + u_xxxx = 0 (named in
+ *           Sec. 2 among the equations the swept rule has been applied to),
+ *           binary64, forward Euler with central differences on a five-point
+ *           stencil: s_k = (u_{k+1} - u_k) + (u_{k-1} - u_k),
+ *           q = (s_{i+1} - s_i) + (s_{i-1} - s_i),
+ *           u' = u - ((a (f_{i+1} - f_{i-1}) + b s_i) + c q), f = 0.5 (u u),
+ *           a = dt / (2 dx), b = dt / dx^2, c = dt / dx^4.  One sub-step of
+ *           radius 2 per time step.  Not available in the batched launch.
  *
  * Precisions:
  *   *_F64 : binary64 throughout.
@@ -36,6 +44,7 @@
  *   SW_EULER_F64, SW_EULER_F64_FLAT : double rho[n], m[n], E[n]
  *                                     (m = rho*u, E = total energy)
  *   SW_EULER_F32, SW_EULER_F32_FLAT : float rho[n], m[n], E[n], c_rho[n], c_m[n], c_E[n]
+ *   SW_KS_F64    : double u[n]
  * The buffer is device memory of the current HIP device, at least
  * sw_state_bytes() long and 16-byte aligned.  It is read as the state at step
  * 0 and overwritten in place with the state at step n_steps.  Before the first
@@ -84,7 +93,8 @@ typedef enum {
     SW_EULER_F64 = 2,       /* lengthened layout: four 3-point sub-steps per step */
     SW_EULER_F32 = 3,
     SW_EULER_F64_FLAT = 4,  /* flattened layout: two 5-point sub-steps per step  */
-    SW_EULER_F32_FLAT = 5
+    SW_EULER_F32_FLAT = 5,
+    SW_KS_F64 = 6           /* Kuramoto-Sivashinsky, binary64 (see above)        */
 } sw_equation;
 
 typedef enum {
@@ -98,7 +108,8 @@ typedef void *sw_stream;
 /* Optional launch controls of swept_solve_ex / naive_solve_ex.
  *   width           : triangle width W in cells (swept only).  0 = library
  *                     choice.  Valid W: a multiple of 2R (R = 2 for the
- *                     flattened layout, else 1), W divides n_cells,
+ *                     flattened layout and Kuramoto-Sivashinsky, else 1),
+ *                     W divides n_cells,
  *                     n_cells / W >= 2, W <= sw_max_width(eq).
  *   threads         : workgroup size of the swept phase kernels: 64, 128,
  *                     256 or 512 (0 = library choice, sw_default_threads).
@@ -138,7 +149,8 @@ size_t sw_state_bytes(int eq, int64_t n_cells);
 
 /* Bytes of working arrays a call needs: the swept method holds two copies of
  * the per-cell working struct (heat F64 16 B, heat F32 12 B, Euler F64 56 B,
- * Euler F32 44 B, flattened Euler F64 48 B, F32 36 B per cell); the naive
+ * Euler F32 44 B, flattened Euler F64 48 B, F32 36 B, Kuramoto-Sivashinsky
+ * 16 B per cell); the naive
  * method holds the second time level (heat) or the predictor state (and, for
  * the lengthened layout, the pressure ratio).  `width` is
  * unused by either method and may be 0.  0 for invalid arguments. */
@@ -153,7 +165,8 @@ int sw_max_width(int eq);
 /* The width swept_solve picks when none is given and the autotuner has
  * recorded none (see sw_tuned_width): the largest valid width (a multiple of
  * 2R dividing n_cells with n_cells / W >= 2) not above the preferred width
- * of `eq` -- heat 2048, Euler 1024 (flattened binary32 2048), measured on
+ * of `eq` -- heat and Kuramoto-Sivashinsky 2048, Euler 1024 (flattened
+ * binary32 2048), measured on
  * MI355X.  0 when there is none. */
 int sw_default_width(int eq, int64_t n_cells);
 

@@ -19,10 +19,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswept.so")
 
 # equation x precision x layout ids (sw_equation)
-HEAT_F64, HEAT_F32, EULER_F64, EULER_F32, EULER_F64_FLAT, EULER_F32_FLAT = 0, 1, 2, 3, 4, 5
+HEAT_F64, HEAT_F32, EULER_F64, EULER_F32, EULER_F64_FLAT, EULER_F32_FLAT, KS_F64 = range(7)
 EQUATIONS = {"heat_f64": HEAT_F64, "heat_f32": HEAT_F32,
              "euler_f64": EULER_F64, "euler_f32": EULER_F32,
-             "euler_f64_flat": EULER_F64_FLAT, "euler_f32_flat": EULER_F32_FLAT}
+             "euler_f64_flat": EULER_F64_FLAT, "euler_f32_flat": EULER_F32_FLAT, "ks_f64": KS_F64}
 # methods (sw_method)
 METHOD_SWEPT, METHOD_NAIVE = 0, 1
 # status codes (sw_status)
@@ -369,12 +369,13 @@ def substeps(eq: int) -> int:
 
 
 def radius(eq: int) -> int:
-    """Stencil radius of one sub-step (2 for the flattened Euler layout)."""
-    return 2 if eq in (EULER_F64_FLAT, EULER_F32_FLAT) else 1
+    """Stencil radius of one sub-step (2 for the flattened Euler layout and
+    Kuramoto-Sivashinsky)."""
+    return 2 if eq in (EULER_F64_FLAT, EULER_F32_FLAT, KS_F64) else 1
 
 
 def is_f64(eq: int) -> bool:
-    return eq in (HEAT_F64, EULER_F64, EULER_F64_FLAT)
+    return eq in (HEAT_F64, EULER_F64, EULER_F64_FLAT, KS_F64)
 
 
 def state_dtype(eq: int):
@@ -385,7 +386,7 @@ def state_dtype(eq: int):
 def state_rows(eq: int) -> int:
     """Arrays of n_cells in the state buffer (see include/swept.h)."""
     return {HEAT_F64: 1, HEAT_F32: 2, EULER_F64: 3, EULER_F32: 6,
-            EULER_F64_FLAT: 3, EULER_F32_FLAT: 6}[eq]
+            EULER_F64_FLAT: 3, EULER_F32_FLAT: 6, KS_F64: 1}[eq]
 
 
 def solve(eq: int, state, n_steps: int, dt: float, dx: float, method: str = "swept",

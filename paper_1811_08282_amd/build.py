@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswept.so")
 SOURCES = ["api.cpp", "tune_batch.cpp", "host_share.cpp", "heat.hip", "euler.hip", "euler_flat.hip",
-           "batch.hip"]
+           "ks.hip", "batch.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

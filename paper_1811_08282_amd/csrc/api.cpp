@@ -40,12 +40,13 @@ int ok()
 
 const char *last_error() { return g_err.c_str(); }
 
-bool valid_eq(int eq) { return eq >= SW_HEAT_F64 && eq <= SW_EULER_F32_FLAT; }
-bool is_euler(int eq) { return eq >= SW_EULER_F64; }
+bool valid_eq(int eq) { return eq >= SW_HEAT_F64 && eq <= SW_KS_F64; }
+bool is_euler(int eq) { return eq >= SW_EULER_F64 && eq <= SW_EULER_F32_FLAT; }
+bool is_heat(int eq) { return eq == SW_HEAT_F64 || eq == SW_HEAT_F32; }
 bool is_flat(int eq) { return eq == SW_EULER_F64_FLAT || eq == SW_EULER_F32_FLAT; }
 bool is_f32(int eq) { return eq == SW_HEAT_F32 || eq == SW_EULER_F32 || eq == SW_EULER_F32_FLAT; }
 int substeps(int eq) { return is_flat(eq) ? 2 : (is_euler(eq) ? 4 : 1); }
-int radius(int eq) { return is_flat(eq) ? 2 : 1; }
+int radius(int eq) { return (is_flat(eq) || eq == SW_KS_F64) ? 2 : 1; }
 
 constexpr int64_t kMaxCells = (int64_t)1 << 40;
 constexpr int64_t kMaxWidth = 8192;
@@ -60,6 +61,7 @@ int lds_per_cell(int eq)
     case SW_EULER_F64: return sw::kLdsPerCellEulerF64;
     case SW_EULER_F32: return sw::kLdsPerCellEulerF32;
     case SW_EULER_F64_FLAT: return sw::kLdsPerCellFlatF64;
+    case SW_KS_F64: return sw::kLdsPerCellKsF64;
     default: return sw::kLdsPerCellFlatF32;
     }
 }
@@ -72,6 +74,7 @@ int struct_bytes(int eq)
     case SW_EULER_F64: return sw::kStructBytesEulerF64;
     case SW_EULER_F32: return sw::kStructBytesEulerF32;
     case SW_EULER_F64_FLAT: return sw::kStructBytesFlatF64;
+    case SW_KS_F64: return sw::kStructBytesKsF64;
     default: return sw::kStructBytesFlatF32;
     }
 }
@@ -115,7 +118,7 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int max_width(int eq)
 {
     const int step = 2 * radius(eq);
-    int64_t w = sw::kLdsBytes / lds_per_cell(eq) - sw::lds_tile_cells(!is_euler(eq), 0, radius(eq));
+    int64_t w = sw::kLdsBytes / lds_per_cell(eq) - sw::lds_tile_cells(is_heat(eq), 0, radius(eq));
     if (w > kMaxWidth)
         w = kMaxWidth;
     return (int)(w - w % step);
@@ -140,6 +143,7 @@ size_t state_bytes(int eq, int64_t n)
     switch (eq) {
     case SW_HEAT_F64: return (size_t)n * 8;
     case SW_HEAT_F32: return (size_t)n * 8;
+    case SW_KS_F64: return (size_t)n * 8;
     default: return (size_t)n * 24;  // Euler, every precision and layout
     }
 }
@@ -155,6 +159,7 @@ size_t naive_ws_bytes(int eq, int64_t n)
     case SW_EULER_F64: return round_up((size_t)n * 24, 256) + round_up((size_t)n * 8, 256);
     case SW_EULER_F32: return round_up((size_t)n * 12, 256) + round_up((size_t)n * 8, 256);
     case SW_EULER_F64_FLAT: return round_up((size_t)n * 24, 256);
+    case SW_KS_F64: return round_up((size_t)n * 8, 256);
     default: return round_up((size_t)n * 12, 256);
     }
 }
@@ -269,6 +274,13 @@ int launched(hipError_t e, const char *what)
     return SW_OK;
 }
 
+void ks_coefficients(double dt, double dx, double *a, double *b, double *c)
+{
+    *a = dt / (2.0 * dx);
+    *b = dt / (dx * dx);
+    *c = dt / ((dx * dx) * (dx * dx));
+}
+
 hipError_t swept_phase_launch(int eq, const sw::PhaseLaunch &p, void *state, const void *in,
                               void *out, double dt, double dx, hipStream_t s)
 {
@@ -294,6 +306,13 @@ hipError_t swept_phase_launch(int eq, const sw::PhaseLaunch &p, void *state, con
         e = sw::flat_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out, lam64,
                                      s);
         break;
+    case SW_KS_F64: {
+        double a, b, c;
+        ks_coefficients(dt, dx, &a, &b, &c);
+        e = sw::ks_f64_swept_phase(p, (double *)state, (const double *)in, (double *)out, a, b, c,
+                                   s);
+        break;
+    }
     default:
         e = sw::flat_f32_swept_phase(p, (float *)state, (const float *)in, (float *)out,
                                      (float)lam64, s);
@@ -344,10 +363,11 @@ int run_swept(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
             return launched(e, "swept phase launch");
     }
     if (phases == 1) {
-        // only heat reaches here (one step: final level 1); copy slot 1 (and
-        // the binary32 compensation) from working array A to the state
+        // only heat and Kuramoto-Sivashinsky reach here (one step: final
+        // level 1); copy slot 1 (and the binary32 compensation) from working
+        // array A to the state
         hipError_t e = hipSuccess;
-        if (eq == SW_HEAT_F64) {
+        if (eq == SW_HEAT_F64 || eq == SW_KS_F64) {
             e = hipMemcpyAsync(state, ws_a + (size_t)n * 8, (size_t)n * 8, hipMemcpyDeviceToDevice,
                                s);
         } else if (eq == SW_HEAT_F32) {
@@ -382,6 +402,18 @@ int run_naive(int eq, int64_t n, int64_t steps, double dt, double dx, void *stat
         if (e == hipSuccess && cur != (char *)state)
             e = hipMemcpyAsync(state, cur, (size_t)n * elem, hipMemcpyDeviceToDevice, s);
         return launched(e, "naive heat launch");
+    }
+    if (eq == SW_KS_F64) {
+        double a, b, c;
+        ks_coefficients(dt, dx, &a, &b, &c);
+        double *cur = (double *)state, *nxt = (double *)ws;
+        for (int64_t t = 0; t < steps && e == hipSuccess; ++t) {
+            e = sw::ks_f64_naive_step(cur, nxt, n, a, b, c, s);
+            std::swap(cur, nxt);
+        }
+        if (e == hipSuccess && cur != (double *)state)
+            e = hipMemcpyAsync(state, cur, (size_t)n * 8, hipMemcpyDeviceToDevice, s);
+        return launched(e, "naive Kuramoto-Sivashinsky launch");
     }
     if (eq == SW_EULER_F64) {
         double *q0 = (double *)state;

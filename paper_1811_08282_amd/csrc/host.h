@@ -18,6 +18,7 @@ const char *last_error();
 
 bool valid_eq(int eq);
 bool is_euler(int eq);
+bool is_heat(int eq);
 bool is_flat(int eq);
 bool is_f32(int eq);
 int substeps(int eq);
@@ -39,6 +40,10 @@ int check_device_pointer(const void *p, int *dev_out);
 int launched(hipError_t e, const char *what);
 
 size_t state_bytes(int eq, int64_t n);
+
+// coefficients of the Kuramoto-Sivashinsky step: a = dt / (2 dx),
+// b = dt / dx^2, c = dt / dx^4, in binary64 in this form
+void ks_coefficients(double dt, double dx, double *a, double *b, double *c);
 
 // host threads of a shared solve when the caller gives none, and the most
 constexpr int kDefaultHostThreads = 8;

@@ -35,6 +35,7 @@
 #include "tile_euler.h"
 #include "tile_heat.h"
 #include "tile_job.h"
+#include "tile_ks.h"
 
 namespace sw {
 namespace host {
@@ -334,14 +335,58 @@ void host_flat_tile(const TileJob &jb, std::vector<double> &dbuf, std::vector<T>
     }
 }
 
+// Kuramoto-Sivashinsky (radius 2, two level slots), coefficients a, b, c.
+void host_ks_tile(const TileJob &jb, std::vector<double> &buf, const double abc[3])
+{
+    constexpr int R = kKsRadius;
+    const int w = jb.w;
+    const int wp = w + 2 * R;
+    const int64_t n = jb.n;
+    buf.resize(2 * (size_t)wp);
+    double *s0 = buf.data();
+    double *s1 = s0 + wp;
+    double *state = (double *)jb.state;
+    const double *ws_in = (const double *)jb.ws_in;
+    double *ws_out = (double *)jb.ws_out;
+    for (int i = 0; i < wp; ++i) {
+        const int64_t g = wrap_cell(jb.g0 + i, n);
+        if (jb.first) {
+            s0[i] = state[g];
+        } else {
+            s0[i] = ws_in[g];
+            s1[i] = ws_in[n + g];
+        }
+    }
+    for (int j = jb.j_first; j <= jb.j_last; ++j) {
+        const int m = window_margin(j, R);
+        const int64_t lv = jb.base + j;
+        const double *src = (lv & 1) ? s0 : s1;
+        double *dst = (lv & 1) ? s1 : s0;
+        for (int i = m + R; i < w - m + R; ++i)
+            dst[i] = ks_update(src[i - 2], src[i - 1], src[i], src[i + 1], src[i + 2], abc[0],
+                               abc[1], abc[2]);
+    }
+    const bool top_odd = ((jb.base + jb.j_last) & 1) != 0;
+    for (int i = R; i < w + R; ++i) {
+        const int64_t g = wrap_cell(jb.g0 + i, n);
+        if (jb.last) {
+            state[g] = top_odd ? s1[i] : s0[i];
+        } else {
+            ws_out[g] = s0[i];
+            ws_out[n + g] = s1[i];
+        }
+    }
+}
+
 struct HostScratch {
     std::vector<double> d, d2;
     std::vector<float> f;
 };
 
-void host_tile(int eq, const TileJob &jb, HostScratch &sc)
+void host_tile(int eq, const TileJob &jb, HostScratch &sc, const double ks_abc[3])
 {
     switch (eq) {
+    case SW_KS_F64: host_ks_tile(jb, sc.d, ks_abc); break;
     case SW_HEAT_F64: host_heat_tile<double, false>(jb, sc.d); break;
     case SW_HEAT_F32: host_heat_tile<float, true>(jb, sc.f); break;
     case SW_EULER_F64: host_euler_f64_tile(jb, sc.d); break;
@@ -361,7 +406,8 @@ struct Arr {
 std::vector<Arr> state_arrays(int eq)
 {
     switch (eq) {
-    case SW_HEAT_F64: return {{0, 8}};
+    case SW_HEAT_F64:
+    case SW_KS_F64: return {{0, 8}};
     case SW_HEAT_F32: return {{0, 4}, {4, 4}};
     case SW_EULER_F64:
     case SW_EULER_F64_FLAT: return {{0, 8}, {8, 8}, {16, 8}};
@@ -373,7 +419,8 @@ std::vector<Arr> work_arrays(int eq)
 {
     std::vector<Arr> a;
     switch (eq) {
-    case SW_HEAT_F64: return {{0, 8}, {8, 8}};
+    case SW_HEAT_F64:
+    case SW_KS_F64: return {{0, 8}, {8, 8}};
     case SW_HEAT_F32: return {{0, 4}, {4, 4}, {8, 4}};
     case SW_EULER_F64:
         for (int k = 0; k < 7; ++k)
@@ -530,6 +577,8 @@ int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, voi
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     const double coef = is_euler(eq) ? dt / dx : dt / (dx * dx);
+    double ks_abc[3];
+    ks_coefficients(dt, dx, &ks_abc[0], &ks_abc[1], &ks_abc[2]);
     const double coef_t = is_f32(eq) ? (double)(float)coef : coef;
     std::vector<HostScratch> scratch(P);
     for (int64_t k = 1; k <= phases && e == hipSuccess; ++k) {
@@ -570,7 +619,7 @@ int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, voi
                     jb.first = first;
                     jb.last = last;
                     jb.final_level = pr.base + pr.j_last;
-                    host_tile(eq, jb, scratch[th]);
+                    host_tile(eq, jb, scratch[th], ks_abc);
                 }
             });
         }

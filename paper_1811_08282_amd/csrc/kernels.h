@@ -18,6 +18,7 @@ constexpr int kStructBytesEulerF64 = 56;  // Q0[3], Q1[3], Pr
 constexpr int kStructBytesEulerF32 = 44;  // Q0[3], c[3], Q1[3] (f32), Pr (f64)
 constexpr int kStructBytesFlatF64 = 48;   // Q0[3], Q1[3]
 constexpr int kStructBytesFlatF32 = 36;   // Q0[3], c[3], Q1[3] (f32)
+constexpr int kStructBytesKsF64 = 16;     // u at even / odd levels
 
 // Cells of LDS padding beyond each halo of a heat tile: the ghost lanes of
 // the register-blocked level sweep read (unused) values up to one lane of
@@ -31,6 +32,7 @@ constexpr int kLdsPerCellEulerF64 = 64;  // struct 56 + pressure 8
 constexpr int kLdsPerCellEulerF32 = 52;  // struct 44 + pressure 8
 constexpr int kLdsPerCellFlatF64 = 48;   // struct only: pressures, ratios, fluxes by lane shifts
 constexpr int kLdsPerCellFlatF32 = 36;   // struct only
+constexpr int kLdsPerCellKsF64 = 16;     // struct only
 
 // LDS cells of one tile of width w with stencil radius `radius`: the tile, its
 // halos and, for heat, the padding.
@@ -98,5 +100,12 @@ hipError_t flat_f32_swept_phase(const PhaseLaunch &p, float *state, const float 
                                 float *ws_out, float lam, hipStream_t s);
 hipError_t flat_f32_naive_substep(int t, float *q0c, float *q1, int64_t n, float lam,
                                   hipStream_t s);
+
+// Kuramoto-Sivashinsky, binary64.  state: u[n]; ws: slot0[n], slot1[n];
+// a = dt / (2 dx), b = dt / dx^2, c = dt / dx^4.
+hipError_t ks_f64_swept_phase(const PhaseLaunch &p, double *state, const double *ws_in,
+                              double *ws_out, double a, double b, double c, hipStream_t s);
+hipError_t ks_f64_naive_step(const double *u, double *v, int64_t n, double a, double b, double c,
+                             hipStream_t s);
 
 } // namespace sw

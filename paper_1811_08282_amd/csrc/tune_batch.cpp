@@ -260,6 +260,9 @@ int prepare_batch(int n_problems, const sw_problem *problems, PreparedBatch *pb)
         int rc = check_common(p.eq, p.n_cells, p.n_steps, p.dt, p.dx, p.d_state, 4);
         if (rc)
             return fail(rc, "problem %d: %s", i, last_error());
+        if (p.eq == SW_KS_F64)
+            return fail(SW_ERR_UNSUPPORTED,
+                        "problem %d: the batched launch has no Kuramoto-Sivashinsky tile body", i);
         if (p.width && !width_ok(p.eq, p.n_cells, p.width))
             return fail(SW_ERR_ARG, "problem %d: width %d invalid for n_cells %lld", i, p.width,
                         (long long)p.n_cells);
@@ -291,7 +294,7 @@ int prepare_batch(int n_problems, const sw_problem *problems, PreparedBatch *pb)
         pb->widths[i] = w;
         pb->array_off[i] = arrays;
         arrays += 2 * swept_copy_bytes(p.eq, p.n_cells);
-        pb->max_lds = std::max(pb->max_lds, (size_t)sw::lds_tile_cells(!is_euler(p.eq), w, b.radius) *
+        pb->max_lds = std::max(pb->max_lds, (size_t)sw::lds_tile_cells(is_heat(p.eq), w, b.radius) *
                                                 (size_t)lds_per_cell(p.eq));
         all64 = all64 && p.eq == SW_HEAT_F64;
         all32 = all32 && p.eq == SW_HEAT_F32;
@@ -797,6 +800,9 @@ static int batch_autotune_impl(int n_problems, sw_problem *problems, int64_t pro
         int rc = check_common(p.eq, p.n_cells, p.n_steps, p.dt, p.dx, p.d_state, 4);
         if (rc)
             return fail(rc, "problem %d: %s", i, last_error());
+        if (p.eq == SW_KS_F64)
+            return fail(SW_ERR_UNSUPPORTED,
+                        "problem %d: the batched launch has no Kuramoto-Sivashinsky tile body", i);
         if (p.width && !width_ok(p.eq, p.n_cells, p.width))
             return fail(SW_ERR_ARG, "problem %d: width %d invalid for n_cells %lld", i, p.width,
                         (long long)p.n_cells);

@@ -14,6 +14,12 @@ the paper's shapes stand in for them:
   (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1), i.e. conserved
   (rho, m, E) = (1, 0, 2.5) | (0.125, 0, 0.25) with gamma = 1.4.
 * batch -- many independent problems with log-uniform lengths.
+* ks    -- the Kuramoto-Sivashinsky equation (no workload in the paper): the
+  heat recipe's random modes scaled by 0.1, dt = 0.02, dx = 1
+  (a = 0.01, b = c = 0.02); the modes lie in the band the equation
+  amplifies, and the solution saturates at |u| of about 4 (forward Euler on
+  the central advection term stays stable there; at dt = 0.05 or with
+  unscaled modes it does not).
 """
 from __future__ import annotations
 
@@ -104,15 +110,24 @@ HEAT_LARGE = Workload("heat_f64_n4194304_s20000", "heat", 1 << 22, 20000, 0.25, 
 EULER_LARGE = Workload("euler_f64_n4194304_s10000", "euler", 1 << 22, 10000, 0.1, 1.0, None, 1 << 14)
 HEAT_PREC = Workload("heat_n16777216_s20000", "heat", 1 << 24, 20000, 0.25, 1.0, 4)
 EULER_PREC = Workload("euler_n16777216_s20000", "euler", 1 << 24, 20000, 0.1, 1.0, None, 1 << 14)
+KS_PREC = Workload("ks_n16777216_s20000", "ks", 1 << 24, 20000, 0.02, 1.0, 6)
 
 
 def initial_state(w: Workload) -> np.ndarray:
-    """binary64 initial state of a workload: (n,) for heat, (3, n) for Euler."""
+    """binary64 initial state of a workload: (n,) for heat and
+    Kuramoto-Sivashinsky, (3, n) for Euler."""
+    if w.eq == "ks":
+        return ks_ic(w.n, w.seed)
     if w.eq == "heat":
         if w.n == 1024:
             return heat_ic(w.n, w.seed, kmax=32, log_uniform=False)
         return heat_ic(w.n, w.seed)
     return sod_tiled(w.n, w.tile)
+
+
+def ks_ic(n: int, seed: int) -> np.ndarray:
+    """Kuramoto-Sivashinsky initial condition: the heat modes scaled by 0.1."""
+    return 0.1 * heat_ic(n, seed)
 
 
 @dataclass(frozen=True)

@@ -252,3 +252,18 @@ def test_work_factor_checked_on_host():
     o = sw._opts(work_factor=2)
     rc = sw.load().naive_solve_ex(sw.HEAT_F64, 1024, 5, 0.25, 1.0, FAKE, None, ctypes.byref(o))
     assert rc == sw.SW_ERR_ARG and "swept" in sw.last_error()
+
+
+def test_ks_sizes_widths_and_batch_refusal():
+    n = 1 << 12
+    assert sw.sw_state_bytes(sw.KS_F64, n) == 8 * n
+    assert sw.sw_workspace_bytes(sw.KS_F64, n, 0, 0) == 2 * 16 * n  # two 16-byte slots
+    assert sw.sw_default_width(sw.KS_F64, 1 << 24) == 2048
+    assert sw.sw_default_width(sw.KS_F64, 24) == 12          # radius 2: multiples of 4
+    assert sw.sw_default_width(sw.KS_F64, 18) == 0
+    rc = sw.swept_solve_ex(sw.KS_F64, 1024, 5, 0.05, 1.0, FAKE, None, width=6)
+    assert rc == sw.SW_ERR_ARG                                 # not a multiple of 4
+    probs = (sw.sw_problem * 1)()
+    probs[0] = sw.sw_problem(sw.KS_F64, 0, 4096, 10, 0.05, 1.0, FAKE)
+    assert sw.load().sw_batch_workspace_bytes(1, probs) == 0
+    assert "Kuramoto" in sw.last_error()

@@ -18,6 +18,8 @@ pytestmark = pytest.mark.gpu
 def _oracle(eq, host, steps, dt):
     if eq == sw.HEAT_F64:
         return oracle.heat_f64(host[0], steps, dt).reshape(1, -1)
+    if eq == sw.KS_F64:
+        return oracle.ks_f64(host[0], steps, dt, 1.0).reshape(1, -1)
     if eq == sw.HEAT_F32:
         return np.stack(oracle.heat_f32(host[0], host[1], steps, dt))
     if eq in (sw.EULER_F64, sw.EULER_F64_FLAT):
@@ -34,6 +36,7 @@ CASES = [
     (sw.EULER_F64, 8192, 512, 300, 1, 3), (sw.EULER_F64, 8192, 512, 77, 5, 2),
     (sw.EULER_F32, 8192, 512, 300, 2, 2),
     (sw.EULER_F64_FLAT, 8192, 512, 300, 1, 3), (sw.EULER_F32_FLAT, 8192, 512, 300, 2, 2),
+    (sw.KS_F64, 8192, 512, 500, 1, 3), (sw.KS_F64, 8192, 512, 129, 4, 2),
 ]
 
 
@@ -42,10 +45,13 @@ def test_shared_solve_equals_swept_solve_and_oracle(eq, n, width, steps, wf, thr
     import torch
     if eq in (sw.HEAT_F64, sw.HEAT_F32):
         q0, dt = heat_ic(n, n + steps), 0.25
+    elif eq == sw.KS_F64:
+        q0, dt = 0.1 * heat_ic(n, n + steps), 0.02
     else:
         q0, dt = sod_tiled(n, 2048), 0.1
     host = pack(sw.EULER_F32 if eq == sw.EULER_F32_FLAT else
-                (sw.EULER_F64 if eq == sw.EULER_F64_FLAT else eq), q0)
+                (sw.EULER_F64 if eq == sw.EULER_F64_FLAT else
+                 (sw.HEAT_F64 if eq == sw.KS_F64 else eq)), q0)
     announce("host share", eq, n, width, steps, "WF", wf, "threads", threads)
     a = torch.from_numpy(np.ascontiguousarray(host)).cuda()
     b = a.clone()
