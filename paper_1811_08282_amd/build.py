@@ -53,6 +53,21 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_test_helpers(verbose: bool = False) -> None:
+    """tests/librn_check.so: the kernel tests/test_gpu_rn_ops.py runs the
+    rounded-to-nearest sequences of the Euler tiles with."""
+    src = os.path.join(ROOT, "tests", "rn_check.hip")
+    out = os.path.join(ROOT, "tests", "librn_check.so")
+    cmd = [hipcc(), *HIP_FLAGS, "-o", out + ".tmp", src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        sys.stderr.write(proc.stdout + proc.stderr)
+        raise RuntimeError("hipcc failed building tests/librn_check.so")
+    os.replace(out + ".tmp", out)
+
+
 if __name__ == "__main__":
     build(verbose=True)
     print(LIB)

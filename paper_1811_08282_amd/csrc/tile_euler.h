@@ -33,19 +33,13 @@
 
 #include "geom.h"
 #include "lanes.h"
+#include "rn_ops.h"
 #include "tile_job.h"
 
 namespace sw {
 
 constexpr double kGamma = 1.4;
 constexpr double kGm1 = 0.4;
-
-__host__ __device__ __forceinline__ double limiter(double q)
-{
-    if (q > 0.0)
-        return q < 1.0 ? q : 1.0;
-    return 0.0;
-}
 
 __host__ __device__ __forceinline__ double ratio(double pm, double pc, double pp)
 {
@@ -71,12 +65,13 @@ __host__ __device__ __forceinline__ void face64(double a0, double a1, double a2,
     const double d0 = b0 - a0, d1 = b1 - a1, d2 = b2 - a2;
     const double l0 = a0 + hl * d0, l1 = a1 + hl * d1, l2 = a2 + hl * d2;
     const double r0 = b0 - hr * d0, r1 = b1 - hr * d1, r2 = b2 - hr * d2;
-    const double vl = l1 / l0;
+    RnDiv dl, dr;  // l0 and r0 each divide twice
+    const double vl = rn_div_keep(l1, l0, dl);
     const double pl = kGm1 * (l2 - 0.5 * (l1 * vl));
-    const double vr = r1 / r0;
+    const double vr = rn_div_keep(r1, r0, dr);
     const double pr = kGm1 * (r2 - 0.5 * (r1 * vr));
-    const double al = sqrt((kGamma * pl) / l0);
-    const double ar = sqrt((kGamma * pr) / r0);
+    double al, ar;
+    rn_sqrt2(rn_div_again(kGamma * pl, dl), rn_div_again(kGamma * pr, dr), al, ar);
     const double sl = fabs(vl) + al;
     const double sr = fabs(vr) + ar;
     const double hs = 0.5 * (sl > sr ? sl : sr);
@@ -207,11 +202,12 @@ __host__ __device__ __forceinline__ void face32(float a0, float a1, float a2, fl
     const float r0 = b0 - hr * d0, r1 = b1 - hr * d1, r2 = b2 - hr * d2;
     const double rl = (double)l0, ml = (double)l1, el = (double)l2;
     const double rr = (double)r0, mr = (double)r1, er = (double)r2;
-    const double vl64 = ml / rl, vr64 = mr / rr;
+    RnDiv dl, dr;
+    const double vl64 = rn_div_keep(ml, rl, dl), vr64 = rn_div_keep(mr, rr, dr);
     const double pl64 = kGm1 * (el - 0.5 * (ml * vl64));
     const double pr64 = kGm1 * (er - 0.5 * (mr * vr64));
-    const double al64 = sqrt((kGamma * pl64) / rl);
-    const double ar64 = sqrt((kGamma * pr64) / rr);
+    double al64, ar64;
+    rn_sqrt2(rn_div_again(kGamma * pl64, dl), rn_div_again(kGamma * pr64, dr), al64, ar64);
     const float vl = (float)vl64, pl = (float)pl64, al = (float)al64;
     const float vr = (float)vr64, pr = (float)pr64, ar = (float)ar64;
     const float sl = fabsf(vl) + al;
