@@ -20,6 +20,7 @@ import pytest
 import oracle
 import paper_1811_08282_amd as sw
 from paper_1811_08282_amd import workloads as wl
+import batch_oracle as bo
 from gpu_util import announce, pack, record, rel_inf, run
 
 pytestmark = pytest.mark.gpu
@@ -299,80 +300,37 @@ def test_batch_4096_problems_autotune(eq_heat, eq_euler):
            full_run_ms={str(t[3]): t[0] for t in timed}, chosen_threads=threads)
 
 
-def _oracle_subset(probs, count=128, seed=128):
-    """`count` problems drawn across the length range: the problems sorted by
-    length are cut into `count` strata of equal size and one problem is drawn
-    from each (seeded); the longest heat and the longest Euler problem (the
-    widest tiles the tuner picks) replace the draws of the last two strata."""
-    rng = np.random.default_rng(seed)
-    order = np.argsort([p.n for p in probs], kind="stable")
-    strata = np.array_split(order, count)
-    pick = [int(rng.choice(s)) for s in strata]
-    longest_heat = max((i for i, p in enumerate(probs) if p.eq == "heat"), key=lambda i: probs[i].n)
-    longest_euler = max((i for i, p in enumerate(probs) if p.eq != "heat"),
-                        key=lambda i: probs[i].n)
-    pick[-2:] = [longest_heat, longest_euler]
-    return sorted(set(pick))
-
-
-# cells a cell's value after one time step depends on, per side: heat 1;
-# Euler 4 (the corrector reads the predictor within 2 cells, which read the
-# old state within 2)
-_CONE = {sw.HEAT_F64: 1, sw.HEAT_F32: 1, sw.EULER_F64: 4, sw.EULER_F32: 4}
-
-
-def _oracle_sample(eq, host, steps, threads=15):
-    """Oracle values of one batch problem: the whole problem when it is no
-    longer than its dependency cone, else one window of 16 cells straddling
-    the periodic seam, stepped on the oracle from the exact cone around it
-    (2 * cone * steps + 16 cells, a ring whose own wrap cannot reach the
-    centre).  Returns (cells, values) with values shaped like host[:, cells]."""
-    n = host.shape[1]
-    reach = _CONE[eq] * steps + 4
-    if n <= 2 * reach + 64:
-        idx = np.arange(n)
-        windows = [(idx, slice(0, n))]
-    else:
-        span, s0 = 16, n - 8
-        windows = [(np.arange(s0 - reach, s0 + span + reach) % n, slice(reach, reach + span))]
-    cells, vals = [], []
-    for idx, keep in windows:
-        h = host[:, idx]
-        if eq == sw.HEAT_F64:
-            out = oracle.heat_f64(h[0], steps, 0.25, threads=threads).reshape(1, -1)
-        elif eq == sw.EULER_F64:
-            out = oracle.euler_f64(h, steps, 0.1, threads=threads)
-        elif eq == sw.HEAT_F32:
-            out = np.stack(oracle.heat_f32(h[0], h[1], steps, 0.25, threads=threads))
-        else:
-            q, c = oracle.euler_f32(h[:3], h[3:], steps, 0.1, threads=threads)
-            out = np.concatenate([q, c])
-        cells.append(idx[keep])
-        vals.append(out[:, keep])
-    return np.concatenate(cells), np.concatenate(vals, axis=1)
-
-
 @pytest.mark.parametrize("eq_heat,eq_euler", [(sw.HEAT_F64, sw.EULER_F64),
                                               (sw.HEAT_F32, sw.EULER_F32)])
 def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
     """The batched workload at full size in one persistent launch, with the
     launch the tuning test chose (the library defaults if it did not run).
     Every problem must equal its own swept solve (phase launches, a different
-    schedule of the same tile bodies); 128 problems drawn across the length
-    range, the longest heat and Euler problems among them, are also checked
-    against the oracle (whole problems, or exact dependency-cone windows of
-    the long ones), which runs on the host threads while the GPU works.
+    schedule of the same tile bodies).  128 problems drawn across the length
+    range, the longest heat and Euler problems among them, must equal the
+    oracle (whole problems, or exact dependency-cone windows of the long
+    ones): through the digests tests/golden/make_batch_oracle.py stored from
+    the oracle, and the two longest also against the oracle stepped live on
+    the host threads while the GPU works.
     (A classic solve of every problem would take 2 * 10^7 launches.)"""
     import torch
     from concurrent.futures import ThreadPoolExecutor
+    pair = "f64" if sw.is_f64(eq_heat) else "f32"
     probs, tensors, hosts, specs = _batch_specs(eq_heat, eq_euler)
-    subset = _oracle_subset(probs)
+    golden = bo.load_golden()
+    assert golden["steps"] == 5000
+    rows = golden["pairs"][pair]["problems"]
+    subset = bo.subset(probs)
     assert len(subset) >= 120
-    # one background worker steps the subset, longest problems first, while
-    # this thread drives the GPU (the oracle call releases the interpreter lock)
+    assert subset == golden["pairs"][pair]["subset"], \
+        "the batch subset changed: rerun tests/golden/make_batch_oracle.py"
+    for r in rows:
+        assert probs[r["problem"]].n == r["n"] and specs[r["problem"]]["eq"] == r["eq"], \
+            "the batched workload changed: rerun tests/golden/make_batch_oracle.py"
+    live = [max((i for i in subset if probs[i].eq == kind), key=lambda i: probs[i].n)
+            for kind in ("heat", "euler")]
     pool = ThreadPoolExecutor(max_workers=1)
-    futures = {i: pool.submit(_oracle_sample, specs[i]["eq"], hosts[i], 5000)
-               for i in sorted(subset, key=lambda i: -probs[i].n)}
+    futures = {i: pool.submit(bo.sample, specs[i]["eq"], hosts[i], 5000, 15) for i in live}
     widths, bpc, threads = _BATCH_CHOICE.get(sw.is_f64(eq_heat), (None, 0, 0))
     if widths:
         for s, w in zip(specs, widths):
@@ -405,20 +363,27 @@ def test_batch_4096_problems_5000_steps(eq_heat, eq_euler):
     ms = start.elapsed_time(stop)
     cells = sum(p.n for p in probs)
     b.close()
-    announce("fullsize batch: waiting for the oracle subset")
+    # the oracle digests of all 128
     checked_widths = set()
-    for k, i in enumerate(sorted(subset, key=lambda i: -probs[i].n)):
+    bad = []
+    for r in rows:
+        i = r["problem"]
+        vals = finals[i][:, bo.sample_cells(specs[i]["eq"], probs[i].n)]
+        assert vals.shape[1] == r["cells"]
+        if bo.digest(vals) != r["sha256"]:
+            bad.append((i, probs[i].n, widths[i], [float(x).hex() for x in vals[:, 0]], r["first"]))
+        checked_widths.add((probs[i].eq, widths[i]))
+    assert not bad, bad[:4]
+    announce("fullsize batch: oracle digests of", len(rows), "problems equal; live oracle")
+    for i in live:
         sampled, want = futures[i].result()
         assert np.array_equal(finals[i][:, sampled], want), (i, probs[i].n, widths[i])
-        checked_widths.add((probs[i].eq, widths[i]))
-        if k % 8 == 7:
-            announce("fullsize batch: oracle subset", k + 1, "of", len(subset), "equal")
     pool.shutdown()
     tag = 'f64' if sw.is_f64(eq_heat) else 'f32'
     record(f"batch_4096x5000_{tag}", ms=ms, cells=cells,
            cell_updates_per_s=cells * 5000 / (ms * 1e-3), blocks_per_cu=bpc, threads=threads,
            distinct_widths=len(set(widths)), widest=max(widths), narrowest=min(widths),
-           oracle_checked=len(subset), oracle_widths=sorted(checked_widths))
+           oracle_checked=len(rows), oracle_live=len(live), oracle_widths=sorted(checked_widths))
     # the widest tile of each equation in the batch was among the oracle checks
     for kind in ("heat", "euler"):
         wmax = max(w for p, w in zip(probs, widths) if (p.eq == "heat") == (kind == "heat"))
