@@ -104,12 +104,12 @@ PERSISTENT_SOURCES = ["batch.hip", "batch.h", "tile_heat.h", "geom.h", "tile_job
 KERNEL_SOURCES = {
     sw.HEAT_F64: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h", "lanes.h", "kernels.h"],
     sw.HEAT_F32: ["tile_heat.h", "heat.hip", "geom.h", "tile_job.h", "lanes.h", "kernels.h"],
-    sw.EULER_F64: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h", "lanes.h"],
-    sw.EULER_F32: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h", "lanes.h"],
+    sw.EULER_F64: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h", "lanes.h", "rn_ops.h"],
+    sw.EULER_F32: ["tile_euler.h", "euler.hip", "geom.h", "tile_job.h", "lanes.h", "rn_ops.h"],
     sw.EULER_F64_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h",
-                        "lanes.h"],
+                        "lanes.h", "rn_ops.h"],
     sw.EULER_F32_FLAT: ["tile_flat.h", "tile_euler.h", "euler_flat.hip", "geom.h", "tile_job.h",
-                        "lanes.h"],
+                        "lanes.h", "rn_ops.h"],
     sw.KS_F64: ["tile_ks.h", "ks.hip", "geom.h", "tile_job.h", "kernels.h"],
 }
 
