@@ -55,17 +55,21 @@ def build(verbose: bool = False) -> str:
 
 def build_test_helpers(verbose: bool = False) -> None:
     """tests/librn_check.so: the kernel tests/test_gpu_rn_ops.py runs the
-    rounded-to-nearest sequences of the Euler tiles with."""
-    src = os.path.join(ROOT, "tests", "rn_check.hip")
-    out = os.path.join(ROOT, "tests", "librn_check.so")
-    cmd = [hipcc(), *HIP_FLAGS, "-o", out + ".tmp", src]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    proc = subprocess.run(cmd, capture_output=True, text=True)
-    if proc.returncode != 0:
-        sys.stderr.write(proc.stdout + proc.stderr)
-        raise RuntimeError("hipcc failed building tests/librn_check.so")
-    os.replace(out + ".tmp", out)
+    rounded-to-nearest sequences of the Euler tiles with; tests/lds_probe:
+    the LDS throughput probe whose rates bench.py's LDS roofline uses."""
+    exe_flags = [f for f in HIP_FLAGS if f not in ("-fPIC", "-shared")]
+    for src, out, flags in (("rn_check.hip", "librn_check.so", HIP_FLAGS),
+                            ("lds_probe.hip", "lds_probe", exe_flags)):
+        src = os.path.join(ROOT, "tests", src)
+        out = os.path.join(ROOT, "tests", out)
+        cmd = [hipcc(), *flags, "-o", out + ".tmp", src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        proc = subprocess.run(cmd, capture_output=True, text=True)
+        if proc.returncode != 0:
+            sys.stderr.write(proc.stdout + proc.stderr)
+            raise RuntimeError(f"hipcc failed building {out}")
+        os.replace(out + ".tmp", out)
 
 
 if __name__ == "__main__":
