@@ -49,14 +49,6 @@ VECTOR_PEAK_TFLOPS = {True: 78.6, False: 157.3}  # binary64, binary32
 # ds_write_b128); the port is taken to serve reads and writes one at a time
 LDS_READ_B_PER_CLK = 150.4
 LDS_WRITE_B_PER_CLK = 70.9
-# VALU lanes per clock per CU from the published vector peaks (an FMA lane is
-# two flops): 78.6 TFLOP/s binary64 -> 64 lanes, 157.3 TFLOP/s binary32 ->
-# 128 lanes.  Counter records split the kernel's VALU instructions into
-# 64-bit floating-point ones (add, mul, fma, transcendental) and the rest
-# (32-bit arithmetic, integer, moves, lane shifts), charged at the 32-bit rate
-VALU_LANES_F64 = 64
-VALU_LANES_32 = 128
-
 WORKLOADS = {
     "heat_f64_large": (wl.HEAT_LARGE, sw.HEAT_F64),
     "heat_f64_small": (wl.HEAT_SMALL, sw.HEAT_F64),
@@ -479,23 +471,24 @@ def rooflines(work, eq, schedule, width, threads, ms, rate):
                         "write_bytes_per_cell_update": wr, "source": source,
                         "peak_model": f"reads at {LDS_READ_B_PER_CLK} B/clk/CU and writes at "
                                       f"{LDS_WRITE_B_PER_CLK} B/clk/CU (measured), in turn"}
+    # the binding unit among the algorithmic ones: HBM and LDS bytes, the
+    # scheme's operations against the published vector peak
+    bound = max(units, key=lambda k: units[k]["frac"])
     if counters and counters.get("valu_mix_lane_insts_per_cell_update"):
+        # diagnostic, not a roofline: the instructions the compiler issues for
+        # those operations (a correctly rounded division is about ten), as
+        # measured; a binary64 reciprocal or reciprocal square root holds its
+        # SIMD four times as long as an add (SQ_ACTIVE_INST_VALU exceeds
+        # SQ_INSTS_VALU by three per such instruction in the counter records)
         mix = counters["valu_mix_lane_insts_per_cell_update"]
         total = counters["valu_lane_insts_per_cell_update"]
         n64 = sum(mix.get(k, 0.0) for k in ("add_f64", "mul_f64", "fma_f64", "trans_f64"))
-        n32 = total - n64
-        # pipe time per cell-update in units of one binary64 lane-op
-        eq64 = n64 + n32 * VALU_LANES_F64 / VALU_LANES_32
-        peak = VALU_LANES_F64 * CUS * CLOCK_HZ
         units["valu"] = {
-            "achieved": rate * eq64 / 1e12, "peak": peak / 1e12,
-            "unit": "T binary64-equivalent lane-ops/s", "frac": rate * eq64 / peak,
             "lane_insts_per_cell_update": total, "binary64_lane_insts_per_cell_update": n64,
-            "other_lane_insts_per_cell_update": n32,
+            "transcendental_binary64_lane_insts_per_cell_update": mix.get("trans_f64", 0.0),
             "issue_wave_insts_per_cu_cycle": counters.get("valu_issue_per_cu_cycle"),
-            "peak_model": f"{VALU_LANES_F64} binary64 or {VALU_LANES_32} 32-bit lanes per clock "
-                          f"per CU (the published 78.6 / 157.3 TFLOP/s vector peaks)"}
-    bound = max(units, key=lambda k: units[k]["frac"])
+            "active_per_cu_cycle": counters.get("valu_active_per_cu_cycle"),
+            "source": "counters"}
     traffic = counters.get("hbm_bytes_per_launch") if counters else None
     kernel = ("persistent swept kernel (heat body alone)" if schedule == "persistent"
               else "swept phase kernel")
