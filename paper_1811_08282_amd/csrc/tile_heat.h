@@ -153,18 +153,22 @@ __device__ __forceinline__ void rb_level(T (&v)[2][kRbC], T (&k)[kRbC], int frz,
             nv = v[QR][c] + inc;
             nk = T(0);
         }
-        bool keep = false;
         if constexpr (EDGE) {
-            if constexpr (DOWN)
-                keep = (c == 0 && lane == 0) || (c >= kRbC - frz && lane == 1);
-            else
-                keep = (c == kRbC - 1 && lane == 0) || (c < frz && lane == 1);
+            // cells that can keep their value at this level: lane 0's cell
+            // next to the window, and lane 1's frozen cells
+            const bool ghost = DOWN ? c == 0 : c == kRbC - 1;
+            const bool frozen = DOWN ? c >= kRbC - frz : c < frz;
+            if (ghost || frozen) {
+                const bool keep = (ghost && lane == 0) || (frozen && lane == 1);
+                v[Q][c] = keep ? v[Q][c] : nv;
+                if constexpr (KAHAN)
+                    k[c] = keep ? k[c] : nk;
+                continue;
+            }
         }
-        if (!keep) {
-            v[Q][c] = nv;
-            if constexpr (KAHAN)
-                k[c] = nk;
-        }
+        v[Q][c] = nv;
+        if constexpr (KAHAN)
+            k[c] = nk;
     }
 }
 
@@ -180,15 +184,18 @@ __device__ __forceinline__ void rb_level_row(T (&v)[2][kRbC], T (&k)[kRbC], int 
         rb_level<T, KAHAN, Q, false, false>(v, k, frz, lane, r);
 }
 
-// Levels j in [ja, jz] (at most kRbL, all with j <= 1 or all with j >= 2).
-// Register parity 0 holds LDS slot p0, the parity of the block's virtual
-// first level; virtual level t of the block writes parity t & 1.
-template <typename T, bool KAHAN, int NT>
+// Levels j in [ja, jz] (at most kRbL, all with j <= 1 when WID, all with
+// j >= 2 otherwise).  Register parity 0 holds LDS slot p0, the parity of the
+// block's virtual first level; virtual level t of the block writes parity
+// t & 1.  WID is a template argument so that, with the level loop unrolled,
+// the number of frozen edge cells at each level is a constant and only the
+// cells that can freeze cost a select.
+template <typename T, bool KAHAN, int NT, bool WID>
 __device__ __forceinline__ void heat_rb_block(T *s0, T *s1, T *cc, int w, int64_t base, int ja,
                                               int jz, T r)
 {
     constexpr int NW = NT / 64;
-    const bool wid = jz <= 1;
+    constexpr bool wid = WID;
     const int nl = jz - ja + 1;
     const int a_out = wid ? 1 - jz : ja - 1;
     const int t_lo = wid ? kRbL - nl : 0;
@@ -286,11 +293,11 @@ __device__ __forceinline__ void heat_levels(T *s0, T *s1, T *cc, int w, int64_t 
         if (sz == 0)
             sz = kRbL;
         for (int j = j_first; j <= jw; j += sz, sz = kRbL)
-            heat_rb_block<T, KAHAN, NT>(s0, s1, cc, w, base, j, j + sz - 1, r);
+            heat_rb_block<T, KAHAN, NT, true>(s0, s1, cc, w, base, j, j + sz - 1, r);
     }
     for (int j = j_first > 2 ? j_first : 2; j <= j_last; j += kRbL) {
         const int jz = j + kRbL - 1 < j_last ? j + kRbL - 1 : j_last;
-        heat_rb_block<T, KAHAN, NT>(s0, s1, cc, w, base, j, jz, r);
+        heat_rb_block<T, KAHAN, NT, false>(s0, s1, cc, w, base, j, jz, r);
     }
 }
 
