@@ -471,9 +471,11 @@ def rooflines(work, eq, schedule, width, threads, ms, rate):
                         "write_bytes_per_cell_update": wr, "source": source,
                         "peak_model": f"reads at {LDS_READ_B_PER_CLK} B/clk/CU and writes at "
                                       f"{LDS_WRITE_B_PER_CLK} B/clk/CU (measured), in turn"}
-    # the binding unit among the algorithmic ones: HBM and LDS bytes, the
-    # scheme's operations against the published vector peak
-    bound = max(units, key=lambda k: units[k]["frac"])
+    # how close each unit runs to its ceiling: the algorithmic fractions, and
+    # for the ALU also the share of CU-cycles the counters find it busy (the
+    # scheme's divisions and square roots cost the hardware ten to twenty
+    # instructions each, so its operation count understates the ALU's load)
+    closeness = {k: units[k]["frac"] for k in units}
     if counters and counters.get("valu_mix_lane_insts_per_cell_update"):
         # diagnostic, not a roofline: the instructions the compiler issues for
         # those operations (a correctly rounded division is about ten), as
@@ -489,11 +491,19 @@ def rooflines(work, eq, schedule, width, threads, ms, rate):
             "issue_wave_insts_per_cu_cycle": counters.get("valu_issue_per_cu_cycle"),
             "active_per_cu_cycle": counters.get("valu_active_per_cu_cycle"),
             "source": "counters"}
+        active = counters.get("valu_active_per_cu_cycle")
+        if active is not None:
+            # binary32 instructions issue at up to twice the binary64 rate
+            closeness["alu"] = max(closeness["alu"], active / (1.0 if f64 else 2.0))
+    # the binding unit: the one nearest its ceiling; its fraction is reported
+    # from the algorithmic count
+    bound = max(closeness, key=closeness.get)
     traffic = counters.get("hbm_bytes_per_launch") if counters else None
     kernel = ("persistent swept kernel (heat body alone)" if schedule == "persistent"
               else "swept phase kernel")
     out = {"bound": bound, "achieved": units[bound]["achieved"], "peak": units[bound]["peak"],
            "unit": units[bound]["unit"], "frac": units[bound]["frac"], "traffic": traffic,
+           "closeness_to_ceiling": closeness,
            "kernel": kernel, "launch_ms": launch_ms, "launches_per_step": launches,
            "counters": "profiles/" + f"{leg_label(work, eq)}_"
                        f"{'persistent' if schedule == 'persistent' else 'phase'}_counters.txt"
