@@ -608,25 +608,33 @@ int sw_default_threads(int eq, int width)
 int swept_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx, void *d_state,
                 sw_stream stream)
 {
-    return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, nullptr);
+    return guarded([&] {
+        return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, nullptr);
+    });
 }
 
 int naive_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx, void *d_state,
                 sw_stream stream)
 {
-    return solve(SW_METHOD_NAIVE, eq, n_cells, n_steps, dt, dx, d_state, stream, nullptr);
+    return guarded([&] {
+        return solve(SW_METHOD_NAIVE, eq, n_cells, n_steps, dt, dx, d_state, stream, nullptr);
+    });
 }
 
 int swept_solve_ex(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
                    void *d_state, sw_stream stream, const sw_opts *opts)
 {
-    return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, opts);
+    return guarded([&] {
+        return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, opts);
+    });
 }
 
 int naive_solve_ex(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
                    void *d_state, sw_stream stream, const sw_opts *opts)
 {
-    return solve(SW_METHOD_NAIVE, eq, n_cells, n_steps, dt, dx, d_state, stream, opts);
+    return guarded([&] {
+        return solve(SW_METHOD_NAIVE, eq, n_cells, n_steps, dt, dx, d_state, stream, opts);
+    });
 }
 
 int64_t sw_phase_count(int64_t final_level, int width, int radius)
@@ -715,7 +723,8 @@ int swept_solve_noalloc(int eq, int64_t n_cells, int64_t n_steps, double dt, dou
     sw_opts o{};
     o.d_workspace = ws;
     o.workspace_bytes = SW_NOALLOC_SCRATCH_BYTES;
-    return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, &o);
+    return guarded(
+        [&] { return solve(SW_METHOD_SWEPT, eq, n_cells, n_steps, dt, dx, d_state, stream, &o); });
 }
 
 } // extern "C"

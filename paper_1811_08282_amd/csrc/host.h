@@ -6,6 +6,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <exception>
+#include <new>
+
 #include "../../include/swept.h"
 #include "kernels.h"
 
@@ -15,6 +18,20 @@ namespace host {
 int fail(int code, const char *fmt, ...);
 int ok();
 const char *last_error();
+
+// Run an entry point's body; a C++ exception (host memory or threads
+// exhausted) becomes a status code instead of crossing the C boundary.
+template <typename F>
+int guarded(F f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return fail(SW_ERR_NOMEM, "host memory exhausted");
+    } catch (const std::exception &e) {
+        return fail(SW_ERR_NOMEM, "host resources exhausted: %s", e.what());
+    }
+}
 
 bool valid_eq(int eq);
 bool is_euler(int eq);

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -564,6 +565,7 @@ int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, voi
     char *d_a = (char *)ws;
     char *d_b = d_a + copy;
     const std::vector<Arr> st_arr = state_arrays(eq), ws_arr = work_arrays(eq);
+    std::vector<HostScratch> scratch(P);
     hipEvent_t ev;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
@@ -580,7 +582,6 @@ int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, voi
     double ks_abc[3];
     ks_coefficients(dt, dx, &ks_abc[0], &ks_abc[1], &ks_abc[2]);
     const double coef_t = is_f32(eq) ? (double)(float)coef : coef;
-    std::vector<HostScratch> scratch(P);
     for (int64_t k = 1; k <= phases && e == hipSuccess; ++k) {
         const sw::PhaseRange pr = sw::phase_range(k, final_level, half, R);
         const bool first = (k == 1), last = (k == phases);
@@ -600,10 +601,12 @@ int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, voi
         e = swept_phase_launch(eq, p, state, d_in, d_out, dt, dx, s);
         if (e != hipSuccess)
             break;
-        // the host tiles of this phase, kt consecutive tiles per thread
-        std::vector<std::thread> pool;
-        for (int th = 0; th < P; ++th) {
-            pool.emplace_back([&, th]() {
+        // the host tiles of this phase, kt consecutive tiles per thread; a
+        // thread that cannot be started has its tiles run on this one, and
+        // no exception leaves a worker
+        std::atomic<bool> worker_failed{false};
+        auto work = [&](int th) {
+            try {
                 for (int64_t t = gt + (int64_t)th * kt; t < gt + (int64_t)(th + 1) * kt; ++t) {
                     TileJob jb;
                     jb.state = h_state;
@@ -621,10 +624,28 @@ int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, voi
                     jb.final_level = pr.base + pr.j_last;
                     host_tile(eq, jb, scratch[th], ks_abc);
                 }
-            });
+            } catch (...) {
+                worker_failed = true;
+            }
+        };
+        std::vector<std::thread> pool;
+        int started = 0;
+        try {
+            pool.reserve(P);
+            for (; started < P; ++started)
+                pool.emplace_back(work, started);
+        } catch (...) {
         }
+        for (int th = started; th < P; ++th)
+            work(th);
         for (auto &t : pool)
             t.join();
+        if (worker_failed) {
+            (void)hipStreamSynchronize(s);
+            (void)hipGetLastError();
+            (void)hipEventDestroy(ev);
+            return fail(SW_ERR_NOMEM, "host memory exhausted in a host tile");
+        }
         const Cyc gpu_wrote = {pr.offset, G}, host_wrote = {G + pr.offset, n - G};
         if (last) {
             e = copy_cells(intersect(host_wrote, {0, n}, n), st_arr, n, (char *)state, h_state,

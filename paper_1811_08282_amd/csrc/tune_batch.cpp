@@ -390,16 +390,6 @@ int launch_run(const PreparedBatch &pb, char *ws, const sw_batch_opts *opts, int
                     "batch launch");
 }
 
-template <typename F>
-int guarded(F f)
-{
-    try {
-        return f();
-    } catch (const std::bad_alloc &) {
-        return fail(SW_ERR_NOMEM, "host memory exhausted");
-    }
-}
-
 } // namespace
 
 // ---- batch handle -------------------------------------------------------------
