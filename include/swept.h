@@ -172,8 +172,9 @@ int sw_default_width(int eq, int64_t n_cells);
 
 /* The workgroup size swept_solve uses for tile width `width` when none is
  * given and the autotuner has recorded none: 512 for Euler tiles of 1024
- * cells or more (twice the resident waves per compute unit at the same
- * LDS), else the width rounded up to whole 64-lane waves, at most 256.
+ * cells or more and Kuramoto-Sivashinsky tiles of 2048 or more (twice the
+ * resident waves per compute unit at the same LDS), else the width rounded
+ * up to whole 64-lane waves, at most 256.
  * 0 for an invalid eq or width. */
 int sw_default_threads(int eq, int width);
 

@@ -102,12 +102,12 @@ int preferred_batch_width(int eq)
 }
 
 // workgroup size of a swept phase when the caller gives none: Euler tiles of
-// 1024 cells or more run 512 threads (twice the resident waves per compute
-// unit at the same LDS), everything else W rounded up to whole waves, at
-// most 256
+// 1024 cells or more and Kuramoto-Sivashinsky tiles of 2048 or more run 512
+// threads (twice the resident waves per compute unit at the same LDS;
+// measured faster), everything else W rounded up to whole waves, at most 256
 int default_threads(int eq, int w)
 {
-    if (is_euler(eq) && w >= 1024)
+    if ((is_euler(eq) && w >= 1024) || (eq == SW_KS_F64 && w >= 2048))
         return 512;
     return sw::default_phase_threads(w);
 }

@@ -76,6 +76,8 @@ def test_default_threads():
         assert sw.sw_default_threads(eq, 2048) == 512
         assert sw.sw_default_threads(eq, 512) == 256
         assert sw.sw_default_threads(eq, 100) == 128
+    assert sw.sw_default_threads(sw.KS_F64, 2048) == 512
+    assert sw.sw_default_threads(sw.KS_F64, 1024) == 256
     assert sw.sw_default_threads(sw.HEAT_F64, 1024) == 256
     assert sw.sw_default_threads(sw.HEAT_F32, 2048) == 256
     assert sw.sw_default_threads(sw.HEAT_F64, 2) == 64
