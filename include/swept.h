@@ -182,7 +182,17 @@ int sw_default_threads(int eq, int width);
  * dt, dx: finite and > 0.  n_steps >= 0 (0 is a no-op).  n_cells >= 4.
  * One phase is one launch of n_cells / W workgroups, which HIP bounds at
  * 2^32 - 1 work-items: SW_ERR_ARG when (n_cells / W) * workgroup size
- * exceeds that (a wider tile fixes it). */
+ * exceeds that (a wider tile fixes it).
+ * A heat grid of 2^20 cells or more with at least two phases runs instead as
+ * one persistent launch (the batch kernel holding this one problem, whose
+ * tiles start as soon as the tiles under them are done), when the caller
+ * passes no workspace, workgroup size or work factor and the autotuner has
+ * recorded no launch for it; the result is the same bit for bit.  Its
+ * library-held working arrays are sw_batch_workspace_bytes() of the problem.
+ * A dependency wait of that launch is bounded (10 s, or SW_WAIT_LIMIT_US
+ * microseconds from the environment); if one runs out, which takes other
+ * work holding the GPU's compute units that long, the call, being
+ * asynchronous, cannot return an error: d_state is filled with NaN instead. */
 int swept_solve(int eq, int64_t n_cells, int64_t n_steps, double dt, double dx,
                 void *d_state, sw_stream stream);
 

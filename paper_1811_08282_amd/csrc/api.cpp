@@ -457,6 +457,7 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
         return rc;
     int w = 0;
     int tuned_threads = 0;
+    bool tuned = false;  // the autotuner recorded this launch
     if (method == SW_METHOD_SWEPT) {
         if (o && o->width) {
             if (!width_ok(eq, n, o->width))
@@ -466,7 +467,7 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
                             o->width, (long long)n, max_width(eq));
             w = o->width;
         } else {
-            w = chosen_width(-1, eq, n, &tuned_threads, false);
+            w = chosen_width(-1, eq, n, &tuned_threads, false, &tuned);
             if (!w)
                 return fail(SW_ERR_UNSUPPORTED, "no valid triangle width for n_cells %lld",
                             (long long)n);
@@ -511,9 +512,29 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
     if (rc)
         return rc;
     hipStream_t s = (hipStream_t)stream;
+    void *ws = nullptr;
+    if (method == SW_METHOD_SWEPT && is_heat(eq) && n >= kPersistentHeatCells &&
+        !(o && (o->d_workspace || o->threads || o->work_factor)) && !tuned &&
+        sw::phase_count(steps, w / 2) >= 2) {
+        sw_problem p{};
+        p.eq = eq;
+        p.width = w;
+        p.n_cells = n;
+        p.n_steps = steps;
+        p.dt = dt;
+        p.dx = dx;
+        p.d_state = state;
+        const size_t pneed = persistent_workspace_bytes(p);
+        if (!pneed)
+            return fail(SW_ERR_ARG, "persistent launch: %s", last_error());
+        rc = get_workspace(dev, s, pneed, nullptr, &ws);
+        if (rc)
+            return rc;
+        rc = run_swept_persistent(p, ws, pneed, s);
+        return rc ? rc : ok();
+    }
     const size_t need = (method == SW_METHOD_SWEPT) ? 2 * swept_copy_bytes(eq, n)
                                                     : naive_ws_bytes(eq, n);
-    void *ws = nullptr;
     rc = get_workspace(dev, s, need, o, &ws);
     if (rc)
         return rc;

@@ -186,6 +186,19 @@ __global__ void k_batch_put(char *dst, PutChunk c)
         d[i] = c.data[i];
 }
 
+// After a persistent launch that holds the caller's own state (swept_solve
+// routes large heat grids through one): if the launch aborted a dependency
+// wait, fill the state with all-ones words (a NaN in binary64 and binary32),
+// so that the failure of an asynchronous call shows in its result.
+__global__ void k_poison_on_abort(const int *status, uint32_t *state, int64_t words)
+{
+    if (*status == 0)
+        return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        state[i] = 0xffffffffu;
+}
+
 template <typename T>
 __global__ void k_fill(T *p, int64_t count, T v)
 {
@@ -232,6 +245,14 @@ void launch_persistent(int bodies, int blocks, size_t lds_bytes, hipStream_t s,
 }
 
 } // namespace
+
+hipError_t poison_on_abort(const void *ws, void *state, size_t bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_poison_on_abort, dim3(256), dim3(256), 0, s,
+                       (const int *)((const char *)ws + 8), (uint32_t *)state,
+                       (int64_t)(bytes / 4));
+    return hipGetLastError();
+}
 
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s) { return fill(p, count, v, s); }
 hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s) { return fill(p, count, v, s); }

@@ -79,10 +79,24 @@ int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, voi
 // free the pinned host arrays of shared solves
 void release_host_arrays();
 
+// A heat grid of at least this many cells runs as one persistent launch of
+// the heat-only batch kernel in swept_solve (its phases overlap), unless the
+// caller gives a workspace, a workgroup size or a work factor, or the
+// autotuner recorded a launch for it.
+constexpr int64_t kPersistentHeatCells = (int64_t)1 << 20;
+
+// device workspace of the persistent launch of problem p (0 if p is invalid)
+size_t persistent_workspace_bytes(const sw_problem &p);
+
+// one persistent launch of problem p on stream s, then the abort check that
+// fills p's state with NaN if a dependency wait of the launch ran out
+int run_swept_persistent(const sw_problem &p, void *ws, size_t ws_bytes, hipStream_t s);
+
 // width of a swept solve when the caller gives none: the tuned width of
 // (device, eq, n) if sw_autotune recorded one, else default_width; threads
-// (if not NULL) receives the tuned workgroup size, else default_threads
-int chosen_width(int dev, int eq, int64_t n, int *threads, bool batch);
+// (if not NULL) receives the tuned workgroup size, else default_threads;
+// tuned (if not NULL) tells which of the two it was
+int chosen_width(int dev, int eq, int64_t n, int *threads, bool batch, bool *tuned = nullptr);
 
 } // namespace host
 } // namespace sw

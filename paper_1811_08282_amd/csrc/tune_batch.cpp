@@ -47,6 +47,7 @@ hipError_t batch_launch(const BatchTables &t, int64_t n_flags, int blocks, int t
 // kernels that carry the data in their arguments (capturable, no host buffer
 // has to outlive the call)
 hipError_t batch_put(void *dst, const void *src, size_t bytes, hipStream_t s);
+hipError_t poison_on_abort(const void *ws, void *state, size_t bytes, hipStream_t s);
 hipError_t fill_f64(double *p, int64_t count, double v, hipStream_t s);
 hipError_t fill_f32(float *p, int64_t count, float v, hipStream_t s);
 
@@ -134,8 +135,10 @@ void store_tune_file_locked(const std::string &arch, int eq, int64_t n, const Tu
     fclose(f);
 }
 
-int chosen_width(int dev, int eq, int64_t n, int *threads, bool batch)
+int chosen_width(int dev, int eq, int64_t n, int *threads, bool batch, bool *tuned)
 {
+    if (tuned)
+        *tuned = false;
     {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
         load_tune_file_locked();
@@ -149,12 +152,16 @@ int chosen_width(int dev, int eq, int64_t n, int *threads, bool batch)
             if (it != g_tune.end()) {
                 if (threads)
                     *threads = it->second.threads;
+                if (tuned)
+                    *tuned = true;
                 return it->second.width;
             }
             auto ic = g_tune_class.find(std::make_tuple(arch, eq, size_class(n)));
             if (ic != g_tune_class.end() && width_ok(eq, n, ic->second.width)) {
                 if (threads)
                     *threads = ic->second.threads;
+                if (tuned)
+                    *tuned = true;
                 return ic->second.width;
             }
         }
@@ -530,6 +537,36 @@ int batch_solve(int n_problems, const sw_problem *problems, const sw_batch_opts 
 }
 
 } // namespace
+
+namespace sw {
+namespace host {
+
+size_t persistent_workspace_bytes(const sw_problem &p)
+{
+    PreparedBatch pb;
+    return prepare_batch(1, &p, &pb) == SW_OK ? pb.total : 0;
+}
+
+int run_swept_persistent(const sw_problem &p, void *ws, size_t ws_bytes, hipStream_t s)
+{
+    sw_batch_opts bo{};
+    bo.threads = 256;
+    // the bound of one dependency wait (microseconds); a test forces the
+    // abort path with a tiny one
+    if (const char *v = getenv("SW_WAIT_LIMIT_US")) {
+        const long long us = strtoll(v, nullptr, 10);
+        if (us > 0)
+            bo.wait_limit_us = us;
+    }
+    const int rc = batch_solve(1, &p, &bo, ws, ws_bytes, s);
+    if (rc)
+        return rc;
+    return launched(sw::poison_on_abort(ws, p.d_state, state_bytes(p.eq, p.n_cells), s),
+                    "the abort check of the persistent launch");
+}
+
+} // namespace host
+} // namespace sw
 
 extern "C" {
 
