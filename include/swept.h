@@ -187,7 +187,8 @@ int sw_default_threads(int eq, int width);
  * one persistent launch (the batch kernel holding this one problem, whose
  * tiles start as soon as the tiles under them are done), when the caller
  * passes no workspace, workgroup size or work factor and the autotuner has
- * recorded no launch for it; the result is the same bit for bit.  Its
+ * recorded no launch for it, or recorded this one (workgroup size 0); the
+ * result is the same bit for bit.  Its
  * library-held working arrays are sw_batch_workspace_bytes() of the problem.
  * A dependency wait of that launch is bounded (10 s, or SW_WAIT_LIMIT_US
  * microseconds from the environment); if one runs out, which takes other
@@ -240,8 +241,9 @@ int sw_phase_interval(int64_t k, int64_t final_level, int width, int radius, int
  * steps before a long run, starting from wide blocks (Sec. 6).  sw_autotune
  * times short swept solves on a scratch state (allocated and freed here) over
  * every valid width that is a multiple of 64 (every valid width if there is
- * none) and workgroup sizes 64/128/256/512, and records the fastest for
- * (device architecture, eq, n_cells).  swept_solve and the batch use a
+ * none) and workgroup sizes 64/128/256/512 -- for heat grids of 2^20 cells or
+ * more also swept_solve's one persistent launch, recorded as workgroup size
+ * 0 -- and records the fastest for (device architecture, eq, n_cells).  swept_solve and the batch use a
  * recorded width whenever the caller gives none.  probe_steps = 0 picks
  * enough steps for four phases at the widest candidate.  If the environment
  * variable SWEPT_TUNE_CACHE names a file, recorded widths are appended to it
@@ -250,8 +252,8 @@ int sw_phase_interval(int64_t k, int64_t final_level, int width, int radius, int
 int sw_autotune(int eq, int64_t n_cells, int64_t probe_steps, sw_stream stream, sw_opts *best,
                 double *best_ms_per_update);
 
-/* The width (and workgroup size) recorded for exactly (current device, eq,
- * n_cells); SW_ERR_UNSUPPORTED when none is.  A cell count without a record
+/* The width (and workgroup size; 0 = the persistent launch) recorded for
+ * exactly (current device, eq, n_cells); SW_ERR_UNSUPPORTED when none is.  A cell count without a record
  * of its own takes, in swept_solve and sw_batch_create, the latest record of
  * its size class floor(log2 n_cells) for the same device and eq when that
  * width is valid for it. */

@@ -239,7 +239,8 @@ def sw_release() -> None:
 # ---- autotuner -----------------------------------------------------------------
 
 def sw_autotune(eq, n_cells, probe_steps=0, stream=None):
-    """Returns (width, threads, ms_per_cell_update); raises on failure."""
+    """Returns (width, threads, ms_per_cell_update); threads 0 names the
+    persistent launch (heat grids of 2^20 cells or more).  Raises on failure."""
     best = sw_opts()
     ms = ctypes.c_double()
     rc = load().sw_autotune(eq, n_cells, probe_steps, stream, ctypes.byref(best), ctypes.byref(ms))
@@ -249,7 +250,8 @@ def sw_autotune(eq, n_cells, probe_steps=0, stream=None):
 
 
 def sw_tuned_width(eq, n_cells):
-    """(width, threads) recorded for (current device, eq, n_cells), or None."""
+    """(width, threads) recorded for (current device, eq, n_cells), or None
+    (threads 0: the persistent launch)."""
     w, t = ctypes.c_int(), ctypes.c_int()
     rc = load().sw_tuned_width(eq, n_cells, ctypes.byref(w), ctypes.byref(t))
     return (w.value, t.value) if rc == SW_OK else None

@@ -457,7 +457,7 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
         return rc;
     int w = 0;
     int tuned_threads = 0;
-    bool tuned = false;  // the autotuner recorded this launch
+    bool tuned = false;  // the autotuner recorded this launch (workgroup size 0: persistent)
     if (method == SW_METHOD_SWEPT) {
         if (o && o->width) {
             if (!width_ok(eq, n, o->width))
@@ -514,7 +514,8 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
     hipStream_t s = (hipStream_t)stream;
     void *ws = nullptr;
     if (method == SW_METHOD_SWEPT && is_heat(eq) && n >= kPersistentHeatCells &&
-        !(o && (o->d_workspace || o->threads || o->work_factor)) && !tuned &&
+        !(o && (o->d_workspace || o->threads || o->work_factor)) &&
+        (!tuned || tuned_threads == 0) &&
         sw::phase_count(steps, w / 2) >= 2) {
         sw_problem p{};
         p.eq = eq;

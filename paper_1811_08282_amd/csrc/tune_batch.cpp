@@ -100,6 +100,10 @@ std::string arch_name(int dev)
     return a;
 }
 
+// a tuned record may name the persistent launch (workgroup size 0) only
+// where swept_solve can take it
+bool persistent_ok(int eq, int64_t n) { return is_heat(eq) && n >= kPersistentHeatCells; }
+
 void load_tune_file_locked()
 {
     if (g_tune_loaded)
@@ -116,7 +120,8 @@ void load_tune_file_locked()
     long long n;
     double ms;
     while (fscanf(f, "%63s %d %lld %d %d %lf", arch, &eq, &n, &w, &t, &ms) == 6) {
-        if (valid_eq(eq) && width_ok(eq, n, w) && (t == 64 || t == 128 || t == 256 || t == 512))
+        if (valid_eq(eq) && width_ok(eq, n, w) &&
+            (t == 64 || t == 128 || t == 256 || t == 512 || (t == 0 && persistent_ok(eq, n))))
             record_tune_locked(std::string(arch), eq, (int64_t)n, TuneEntry{w, t, ms});
     }
     fclose(f);
@@ -619,32 +624,43 @@ static int autotune_impl(int eq, int64_t n_cells, int64_t probe_steps, sw_stream
         rc = fail(SW_ERR_HIP, "autotune setup failed");
     }
     const double dt = 0.1, dx = 1.0;
+    // one warm-up solve, then one timed solve: ms per cell-update
+    auto probe = [&](const sw_opts &o, double *per) -> int {
+        int r = swept_solve_ex(eq, n_cells, steps, dt, dx, state, stream, &o);
+        if (r)
+            return r;
+        if (hipEventRecord(e0, s) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SW_ERR_HIP, "hipEventRecord failed");
+        }
+        r = swept_solve_ex(eq, n_cells, steps, dt, dx, state, stream, &o);
+        if (r)
+            return r;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SW_ERR_HIP, "autotune timing failed");
+        }
+        *per = (double)ms / ((double)n_cells * (double)steps);
+        return SW_OK;
+    };
     for (size_t ci = 0; ci < cands.size() && rc == SW_OK; ++ci) {
         const int w = cands[ci];
+        double per = 0.0;
         for (int threads = 512; threads >= 64 && rc == SW_OK; threads /= 2) {
             if (threads > 64 && threads / 2 >= w)
                 continue;  // wider workgroups than the tile only idle
-            sw_opts o{w, threads, ws, wbytes};
-            rc = swept_solve_ex(eq, n_cells, steps, dt, dx, state, stream, &o);  // warm-up
-            if (rc)
-                break;
-            float ms = 0.f;
-            if (hipEventRecord(e0, s) != hipSuccess) {
-                rc = fail(SW_ERR_HIP, "hipEventRecord failed");
-                break;
-            }
-            rc = swept_solve_ex(eq, n_cells, steps, dt, dx, state, stream, &o);
-            if (rc)
-                break;
-            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                (void)hipGetLastError();
-                rc = fail(SW_ERR_HIP, "autotune timing failed");
-                break;
-            }
-            const double per = (double)ms / ((double)n_cells * (double)steps);
-            if (per < top.ms_per_update)
+            rc = probe(sw_opts{w, threads, ws, wbytes}, &per);
+            if (rc == SW_OK && per < top.ms_per_update)
                 top = TuneEntry{w, threads, per};
+        }
+        // the persistent launch, which swept_solve takes for a width given
+        // with no workgroup size and no workspace (recorded as size 0)
+        if (rc == SW_OK && persistent_ok(eq, n_cells)) {
+            rc = probe(sw_opts{w, 0, nullptr, 0}, &per);
+            if (rc == SW_OK && per < top.ms_per_update)
+                top = TuneEntry{w, 0, per};
         }
     }
     if (e0)
