@@ -1,5 +1,5 @@
 """Pins of the Kuramoto-Sivashinsky oracle (u_t + u u_x + u_xx + u_xxxx = 0,
-forward Euler, central differences; the scheme is this build's reading: the
+forward Euler, central differences; the scheme is a chosen reading: the
 paper names the equation, Sec. 2, but gives no scheme).
 
 * Exact rational brute force from the five-point formulas
