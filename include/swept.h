@@ -183,7 +183,7 @@ int sw_default_threads(int eq, int width);
  * One phase is one launch of n_cells / W workgroups, which HIP bounds at
  * 2^32 - 1 work-items: SW_ERR_ARG when (n_cells / W) * workgroup size
  * exceeds that (a wider tile fixes it).
- * A heat grid of 2^20 cells or more with at least two phases runs instead as
+ * A heat grid of 2^20 cells or more with 2 to 2^31 - 2 phases runs instead as
  * one persistent launch (the batch kernel holding this one problem, whose
  * tiles start as soon as the tiles under them are done), when the caller
  * passes no workspace, workgroup size or work factor and the autotuner has

@@ -525,14 +525,16 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
         p.dt = dt;
         p.dx = dx;
         p.d_state = state;
+        // 0 when the batch's limits refuse the problem (2^31 - 2 phases):
+        // the phase launches below take it
         const size_t pneed = persistent_workspace_bytes(p);
-        if (!pneed)
-            return fail(SW_ERR_ARG, "persistent launch: %s", last_error());
-        rc = get_workspace(dev, s, pneed, nullptr, &ws);
-        if (rc)
-            return rc;
-        rc = run_swept_persistent(p, ws, pneed, s);
-        return rc ? rc : ok();
+        if (pneed) {
+            rc = get_workspace(dev, s, pneed, nullptr, &ws);
+            if (rc)
+                return rc;
+            rc = run_swept_persistent(p, ws, pneed, s);
+            return rc ? rc : ok();
+        }
     }
     const size_t need = (method == SW_METHOD_SWEPT) ? 2 * swept_copy_bytes(eq, n)
                                                     : naive_ws_bytes(eq, n);
