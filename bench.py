@@ -12,10 +12,10 @@ binary64 and binary32 + Kahan, the Euler equations in both sub-step layouts,
 reports swept and classic (one launch per sub-step) throughput, their ratio,
 its sampled error against the oracle and its rooflines.
 
-Heat grids of 2^20 cells and more run as one persistent launch per solve
-(the batched launch holding the single problem, ``sw_batch_run``), the other
-workloads one launch per phase (``swept_solve``), the faster schedule of each
-on MI355X.  Every timed solve starts from the initial state, restored from a
+Heat grids of more than 1024 tiles of 1792 cells or more run as one
+persistent launch per solve (the batched launch holding the single problem,
+``sw_batch_run``, as ``swept_solve`` does for them), the other workloads one
+launch per phase (``swept_solve``), the faster schedule of each on MI355X.  Every timed solve starts from the initial state, restored from a
 device copy outside the timed region; times are HIP events on the launch
 stream and the reported time is the median over the timed solves.
 
@@ -514,14 +514,22 @@ def rooflines(work, eq, schedule, width, threads, ms, rate):
 
 # ---- one leg: swept and classic on one workload in one equation id ---------------
 
+def persistent_route(eq, n, width):
+    """The rule swept_solve follows: a heat grid runs as one persistent
+    launch when its tiles are 1792 cells wide or more and more than 1024 in
+    number (measured on MI355X at 6000 steps, binary64, W = 2048: 2.94e12
+    against 2.74e12 cell-updates/s at 2^22 cells, level at 2^21, 1.36e12
+    against 1.73e12 at 2^20; 2048 tiles: 2.9e12 against 2.7e12 at W = 1792,
+    level at W = 1280, 1.9e12 against 2.1e12 at W = 1024)."""
+    return eq in (sw.HEAT_F64, sw.HEAT_F32) and width >= 1792 and n // width > 1024
+
+
 def default_schedule(eq, work):
-    # measured on MI355X: one persistent launch wins or ties for heat grids
-    # of 2^20 cells and more (2^24 x 4000 steps, W = 2048: binary32 3.38e12
-    # against 3.29e12 cell-updates/s, binary64 2.83e12 either way); on a grid
-    # of a few tiles the phase launches are slightly faster, and for Euler
-    # the two are level or the phase launches win
-    big_heat = eq in (sw.HEAT_F64, sw.HEAT_F32) and work.n >= (1 << 20)
-    return "persistent" if big_heat else "phases"
+    # Euler and Kuramoto-Sivashinsky phases last 8-55 ms: the drain between
+    # launches costs little, and for Euler the two are level or the phase
+    # launches win
+    width = sw.sw_default_width(eq, work.n)
+    return "persistent" if persistent_route(eq, work.n, width) else "phases"
 
 
 def run_leg(torch, work, eq, args, reps, naive_reps, warmup, verify=True):
@@ -603,6 +611,45 @@ def width_sweep(torch, work, eq, widths, reps, naive_reps):
             "naive": {"value": updates / (nms * 1e-3), "ms_per_solve": nms, "reps": naive_reps}}
 
 
+# the paper's grid sizes (Sec. 5) among powers of two, and its 6000-step average
+GRID_SIZES = [1 << 12, 1 << 14, 1 << 16, 1 << 18, 500000, 1000000, 1 << 20, 1 << 22, 5000000,
+              10000000, 1 << 24]
+GRID_STEPS = 6000
+
+
+def grid_sweep(torch, eq, sizes, steps, reps):
+    """swept_solve (library width, workgroup size and schedule) against the
+    classic solve over grid sizes, with the state resident in HBM and the way
+    the paper times (allocation and host copies included); every pair of
+    final states compared bit for bit."""
+    rows = []
+    for n in sizes:
+        if eq == sw.HEAT_F64:
+            work = wl.Workload(f"heat_f64_n{n}_s{steps}", "heat", n, steps, 0.25, 1.0, 7)
+        else:
+            work = wl.Workload(f"euler_f64_n{n}_s{steps}", "euler", n, steps, 0.1, 1.0, None,
+                               1 << 14)
+        state0 = pack_state(eq, wl.initial_state(work))
+        updates = n * steps
+        width = sw.sw_default_width(eq, n)
+        sms, _, sdev, _ = time_solves(torch, eq, state0, work, "swept", "phases", 0, 0, reps, 1)
+        nms, _, ndev, _ = time_solves(torch, eq, state0, work, "naive", "phases", 0, 0, reps, 1)
+        same = bool(torch.equal(sdev, ndev))
+        del sdev, ndev
+        sp = paper_style_ms(torch, eq, state0, work, "swept", "phases", 0, 0)
+        npms = paper_style_ms(torch, eq, state0, work, "naive", "phases", 0, 0)
+        row = {"n_cells": n, "width": width,
+               "schedule": "persistent" if persistent_route(eq, n, width) else "phases",
+               "swept": updates / (sms * 1e-3), "classic": updates / (nms * 1e-3),
+               "swept_over_classic": nms / sms, "swept_equals_classic": same,
+               "with_host_copies": {"swept_ms": sp, "classic_ms": npms,
+                                    "swept_over_classic": npms / sp}}
+        log(f"[bench] grid {leg_label(work, eq)}: {json.dumps(row)}")
+        rows.append(row)
+    return {"equation": "heat" if eq == sw.HEAT_F64 else "euler", "precision": "binary64",
+            "time_steps": steps, "reps": reps, "rows": rows}
+
+
 def wf_sweep(torch, work, eq, tiles_per_thread, host_threads, reps):
     """The swept solve shared with host threads (sw_opts.work_factor), against
     the GPU alone, on one workload; each host thread takes k tiles for k in
@@ -661,7 +708,8 @@ def main() -> int:
                     help="workgroup size of the swept kernel (0: library choice)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "phases", "persistent"],
                     help="one launch per phase, or one persistent launch per solve "
-                         "(auto: persistent for heat grids of 2^20 cells and more)")
+                         "(auto: swept_solve's rule, persistent for heat grids of more than "
+                         "1024 tiles of 1792 cells or more)")
     ap.add_argument("--naive-reps", type=int, default=3, help="timed classic solves of heat legs")
     ap.add_argument("--euler-reps", type=int, default=1,
                     help="timed swept and classic solves of each Euler leg")
@@ -669,10 +717,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-naive", action="store_true", help="skip the classic-path timing")
     ap.add_argument("--no-verify", action="store_true", help="skip the sampled oracle checks")
-    ap.add_argument("--sweep", default=None, choices=["c2", "c1", "wf"],
+    ap.add_argument("--sweep", default=None, choices=["c2", "c1", "wf", "grid"],
                     help="width sweep of the 2^22-cell heat workload (c2, widths 64 to the LDS "
-                         "limit), the 1024-cell one at W = 64 (c1), or the GPU work factor of a "
-                         "solve shared with host threads (wf: heat 2^22 cells, Euler 2^24)")
+                         "limit), the 1024-cell one at W = 64 (c1), the GPU work factor of a "
+                         "solve shared with host threads (wf: heat 2^22 cells, Euler 2^24), or "
+                         "swept against classic over grid sizes 2^12 to 2^24 and the paper's "
+                         "5e5 to 1e7 (grid: heat and Euler binary64, 6000 steps)")
     ap.add_argument("--host-threads", type=int, default=8,
                     help="host threads of the work-factor sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -701,6 +751,12 @@ def main() -> int:
         return 0
     sw.load()
 
+    if args.sweep == "grid":
+        res = {"metric": "cell-updates/s",
+               "sweeps": [grid_sweep(torch, sw.HEAT_F64, GRID_SIZES, GRID_STEPS, max(args.steps, 1)),
+                          grid_sweep(torch, sw.EULER_F64, GRID_SIZES, GRID_STEPS, 1)]}
+        print(json.dumps(res), flush=True)
+        return 0
     if args.sweep == "wf":
         res = {"metric": "cell-updates/s",
                "sweeps": [wf_sweep(torch, wl.HEAT_LARGE, sw.HEAT_F64, [1, 2, 4], args.host_threads,

@@ -171,7 +171,7 @@ int sw_max_width(int eq);
 int sw_default_width(int eq, int64_t n_cells);
 
 /* The workgroup size swept_solve uses for tile width `width` when none is
- * given and the autotuner has recorded none: 512 for Euler tiles of 1024
+ * given and the autotuner has recorded none: 512 for Euler tiles of 1000
  * cells or more and Kuramoto-Sivashinsky tiles of 2048 or more (twice the
  * resident waves per compute unit at the same LDS), else the width rounded
  * up to whole 64-lane waves, at most 256.
@@ -183,8 +183,9 @@ int sw_default_threads(int eq, int width);
  * One phase is one launch of n_cells / W workgroups, which HIP bounds at
  * 2^32 - 1 work-items: SW_ERR_ARG when (n_cells / W) * workgroup size
  * exceeds that (a wider tile fixes it).
- * A heat grid of 2^20 cells or more with 2 to 2^31 - 2 phases runs instead as
- * one persistent launch (the batch kernel holding this one problem, whose
+ * A heat grid of more than 1024 tiles of W >= 1792 cells (more than 2^21
+ * cells at W = 2048), with 2 to 2^31 - 2 phases, runs instead as one
+ * persistent launch (the batch kernel holding this one problem, whose
  * tiles start as soon as the tiles under them are done), when the caller
  * passes no workspace, workgroup size or work factor and the autotuner has
  * recorded no launch for it, or recorded this one (workgroup size 0); the
@@ -241,10 +242,11 @@ int sw_phase_interval(int64_t k, int64_t final_level, int width, int radius, int
  * steps before a long run, starting from wide blocks (Sec. 6).  sw_autotune
  * times short swept solves on a scratch state (allocated and freed here) over
  * every valid width that is a multiple of 64 (every valid width if there is
- * none) and workgroup sizes 64/128/256/512 -- for heat grids of 2^20 cells or
- * more also swept_solve's one persistent launch, recorded as workgroup size
- * 0 -- and records the fastest for (device architecture, eq, n_cells).  swept_solve and the batch use a
- * recorded width whenever the caller gives none.  probe_steps = 0 picks
+ * none) and workgroup sizes 64/128/256/512 (at widths where swept_solve
+ * takes its one persistent launch, that launch too, recorded as workgroup
+ * size 0), and records the fastest for (device architecture, eq, n_cells).
+ * swept_solve and the batch use a recorded width whenever the caller gives
+ * none.  probe_steps = 0 picks
  * enough steps for four phases at the widest candidate.  If the environment
  * variable SWEPT_TUNE_CACHE names a file, recorded widths are appended to it
  * and read back by later processes.  Not allowed during stream capture

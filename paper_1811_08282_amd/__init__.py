@@ -240,7 +240,8 @@ def sw_release() -> None:
 
 def sw_autotune(eq, n_cells, probe_steps=0, stream=None):
     """Returns (width, threads, ms_per_cell_update); threads 0 names the
-    persistent launch (heat grids of 2^20 cells or more).  Raises on failure."""
+    persistent launch (heat grids of more than 1024 tiles of 1792 cells or
+    more).  Raises on failure."""
     best = sw_opts()
     ms = ctypes.c_double()
     rc = load().sw_autotune(eq, n_cells, probe_steps, stream, ctypes.byref(best), ctypes.byref(ms))

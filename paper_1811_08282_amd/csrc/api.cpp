@@ -43,6 +43,11 @@ const char *last_error() { return g_err.c_str(); }
 bool valid_eq(int eq) { return eq >= SW_HEAT_F64 && eq <= SW_KS_F64; }
 bool is_euler(int eq) { return eq >= SW_EULER_F64 && eq <= SW_EULER_F32_FLAT; }
 bool is_heat(int eq) { return eq == SW_HEAT_F64 || eq == SW_HEAT_F32; }
+
+bool persistent_route(int eq, int64_t n, int w)
+{
+    return is_heat(eq) && w >= kPersistentMinWidth && n / w > kPersistentMinTiles;
+}
 bool is_flat(int eq) { return eq == SW_EULER_F64_FLAT || eq == SW_EULER_F32_FLAT; }
 bool is_f32(int eq) { return eq == SW_HEAT_F32 || eq == SW_EULER_F32 || eq == SW_EULER_F32_FLAT; }
 int substeps(int eq) { return is_flat(eq) ? 2 : (is_euler(eq) ? 4 : 1); }
@@ -102,12 +107,12 @@ int preferred_batch_width(int eq)
 }
 
 // workgroup size of a swept phase when the caller gives none: Euler tiles of
-// 1024 cells or more and Kuramoto-Sivashinsky tiles of 2048 or more run 512
+// 1000 cells or more and Kuramoto-Sivashinsky tiles of 2048 or more run 512
 // threads (twice the resident waves per compute unit at the same LDS;
 // measured faster), everything else W rounded up to whole waves, at most 256
 int default_threads(int eq, int w)
 {
-    if ((is_euler(eq) && w >= 1024) || (eq == SW_KS_F64 && w >= 2048))
+    if ((is_euler(eq) && w >= 1000) || (eq == SW_KS_F64 && w >= 2048))
         return 512;
     return sw::default_phase_threads(w);
 }
@@ -513,7 +518,7 @@ int solve(int method, int eq, int64_t n, int64_t steps, double dt, double dx, vo
         return rc;
     hipStream_t s = (hipStream_t)stream;
     void *ws = nullptr;
-    if (method == SW_METHOD_SWEPT && is_heat(eq) && n >= kPersistentHeatCells &&
+    if (method == SW_METHOD_SWEPT && persistent_route(eq, n, w) &&
         !(o && (o->d_workspace || o->threads || o->work_factor)) &&
         (!tuned || tuned_threads == 0) &&
         sw::phase_count(steps, w / 2) >= 2) {

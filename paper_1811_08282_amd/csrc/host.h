@@ -79,11 +79,17 @@ int run_swept_shared(int eq, int64_t n, int64_t steps, double dt, double dx, voi
 // free the pinned host arrays of shared solves
 void release_host_arrays();
 
-// A heat grid of at least this many cells runs as one persistent launch of
-// the heat-only batch kernel in swept_solve (its phases overlap), unless the
-// caller gives a workspace, a workgroup size or a work factor, or the
-// autotuner recorded a launch for it.
-constexpr int64_t kPersistentHeatCells = (int64_t)1 << 20;
+// swept_solve runs a heat grid as one persistent launch of the heat-only
+// batch kernel (its phases overlap) when its tiles are at least
+// kPersistentMinWidth cells wide and more than kPersistentMinTiles in number,
+// unless the caller gives a workspace, a workgroup size or a work factor, or
+// the autotuner recorded another launch.  Measured on MI355X: with fewer
+// tiles than the chip holds resident workgroups (1024 at W = 2048), or with
+// narrower tiles (level at W = 1280, behind at 1024), one launch per phase is
+// as fast or faster.
+constexpr int kPersistentMinWidth = 1792;
+constexpr int64_t kPersistentMinTiles = 1024;
+bool persistent_route(int eq, int64_t n, int w);
 
 // device workspace of the persistent launch of problem p (0 if p is invalid)
 size_t persistent_workspace_bytes(const sw_problem &p);

@@ -56,7 +56,7 @@ struct PhaseLaunch {
 };
 
 // Workgroup size of a swept phase for tile width w: whole waves covering the
-// tile, at most 256 (the host raises Euler tiles of 1024 cells and more to 512).
+// tile, at most 256 (the host raises Euler tiles of 1000 cells and more to 512).
 inline int default_phase_threads(int w)
 {
     const int t = ((w + 63) / 64) * 64;

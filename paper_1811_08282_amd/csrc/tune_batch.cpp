@@ -100,10 +100,6 @@ std::string arch_name(int dev)
     return a;
 }
 
-// a tuned record may name the persistent launch (workgroup size 0) only
-// where swept_solve can take it
-bool persistent_ok(int eq, int64_t n) { return is_heat(eq) && n >= kPersistentHeatCells; }
-
 void load_tune_file_locked()
 {
     if (g_tune_loaded)
@@ -120,8 +116,8 @@ void load_tune_file_locked()
     long long n;
     double ms;
     while (fscanf(f, "%63s %d %lld %d %d %lf", arch, &eq, &n, &w, &t, &ms) == 6) {
-        if (valid_eq(eq) && width_ok(eq, n, w) &&
-            (t == 64 || t == 128 || t == 256 || t == 512 || (t == 0 && persistent_ok(eq, n))))
+        const bool sized = t == 64 || t == 128 || t == 256 || t == 512;
+        if (valid_eq(eq) && width_ok(eq, n, w) && (sized || (t == 0 && persistent_route(eq, n, w))))
             record_tune_locked(std::string(arch), eq, (int64_t)n, TuneEntry{w, t, ms});
     }
     fclose(f);
@@ -657,7 +653,7 @@ static int autotune_impl(int eq, int64_t n_cells, int64_t probe_steps, sw_stream
         }
         // the persistent launch, which swept_solve takes for a width given
         // with no workgroup size and no workspace (recorded as size 0)
-        if (rc == SW_OK && persistent_ok(eq, n_cells)) {
+        if (rc == SW_OK && persistent_route(eq, n_cells, w)) {
             rc = probe(sw_opts{w, 0, nullptr, 0}, &per);
             if (rc == SW_OK && per < top.ms_per_update)
                 top = TuneEntry{w, 0, per};

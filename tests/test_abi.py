@@ -70,9 +70,11 @@ def test_width_limits():
 
 
 def test_default_threads():
-    # Euler tiles of 1024 cells and more: 512 threads; else whole waves up to 256
+    # Euler tiles of 1000 cells and more: 512 threads; else whole waves up to 256
     for eq in (sw.EULER_F64, sw.EULER_F32, sw.EULER_F64_FLAT, sw.EULER_F32_FLAT):
         assert sw.sw_default_threads(eq, 1024) == 512
+        assert sw.sw_default_threads(eq, 1000) == 512
+        assert sw.sw_default_threads(eq, 992) == 256
         assert sw.sw_default_threads(eq, 2048) == 512
         assert sw.sw_default_threads(eq, 512) == 256
         assert sw.sw_default_threads(eq, 100) == 128

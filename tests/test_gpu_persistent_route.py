@@ -1,7 +1,7 @@
-"""swept_solve runs heat grids of 2^20 cells and more as one persistent launch
-(the heat-only batch kernel, its phases overlapped) when the caller gives no
-workspace, workgroup size or work factor; with a workgroup size it launches
-once per phase.  Both equal the classic solve bit for bit, in binary64 and
+"""swept_solve runs heat grids of more than 1024 tiles of 1792 cells or more
+as one persistent launch (the heat-only batch kernel, its phases overlapped)
+when the caller gives no workspace, workgroup size or work factor; with a
+workgroup size, fewer tiles or narrower ones it launches once per phase.  Both equal the classic solve bit for bit, in binary64 and
 binary32.  A dependency wait of the persistent launch that runs out (forced
 here from the host with a one-microsecond bound, SW_WAIT_LIMIT_US) leaves the
 caller's state filled with NaN, and the next call runs normally.  The
@@ -18,7 +18,7 @@ from gpu_util import announce, pack
 
 pytestmark = pytest.mark.gpu
 
-N = 1 << 20
+N = 1 << 22  # 2048 tiles of 2048 cells
 
 
 @pytest.mark.parametrize("eq", [sw.HEAT_F64, sw.HEAT_F32])
@@ -60,9 +60,9 @@ def test_aborted_persistent_launch_poisons_the_state():
 
 
 def test_autotune_weighs_the_persistent_launch():
-    """On a heat grid of 2^20 cells the autotuner times the persistent launch
-    beside the workgroup sizes (recorded as size 0); whichever wins,
-    swept_solve with the record equals the classic solve."""
+    """On a heat grid of 2^22 cells the autotuner times the persistent launch
+    beside the workgroup sizes at widths of 1792 and up (recorded as size 0);
+    whichever wins, swept_solve with the record equals the classic solve."""
     import torch
     sw.sw_tune_clear()
     try:
@@ -87,7 +87,7 @@ import paper_1811_08282_amd as sw
 from paper_1811_08282_amd.workloads import heat_ic
 n = 1 << 22
 print('tuned', sw.sw_tuned_width(sw.HEAT_F64, n), sw.sw_tuned_width(sw.EULER_F64, n),
-      sw.sw_tuned_width(sw.HEAT_F64, 1 << 18), flush=True)
+      sw.sw_tuned_width(sw.HEAT_F64, 1 << 21), sw.sw_tuned_width(sw.HEAT_F64, 1 << 23), flush=True)
 t = torch.from_numpy(heat_ic(n, 43).reshape(1, -1).copy()).cuda()
 sw.solve(sw.HEAT_F64, t, 3000, 0.25, 1.0)
 torch.cuda.synchronize()
@@ -100,8 +100,8 @@ def test_tuned_record_selects_the_route(threads, tmp_path):
     """A record read from the tune cache file with workgroup size 0 sends
     swept_solve down the persistent launch (shown by the NaN a 1 us wait
     bound leaves), size 256 down the phase launches (no persistent launch,
-    so nothing to abort).  Size 0 is refused for Euler and for heat grids
-    below 2^20 cells."""
+    so nothing to abort).  Size 0 is refused for Euler, for heat grids of
+    1024 tiles or fewer and for tiles narrower than 1792 cells."""
     import subprocess
     import sys
     import torch
@@ -109,7 +109,8 @@ def test_tuned_record_selects_the_route(threads, tmp_path):
     path = tmp_path / "tune.txt"
     path.write_text(f"{arch} {sw.HEAT_F64} {1 << 22} 2048 {threads} 1e-9\n"
                     f"{arch} {sw.EULER_F64} {1 << 22} 1024 0 1e-9\n"
-                    f"{arch} {sw.HEAT_F64} {1 << 18} 2048 0 1e-9\n")
+                    f"{arch} {sw.HEAT_F64} {1 << 21} 2048 0 1e-9\n"
+                    f"{arch} {sw.HEAT_F64} {1 << 23} 1024 0 1e-9\n")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     env = dict(os.environ, SWEPT_TUNE_CACHE=str(path), SW_WAIT_LIMIT_US="1", PYTHONPATH=root)
     announce("tuned route", threads)
@@ -117,5 +118,5 @@ def test_tuned_record_selects_the_route(threads, tmp_path):
                        text=True, timeout=120)
     assert p.returncode == 0, p.stderr
     lines = dict(line.split(" ", 1) for line in p.stdout.strip().splitlines())
-    assert lines["tuned"] == f"(2048, {threads}) None None"
+    assert lines["tuned"] == f"(2048, {threads}) None None None"
     assert lines["nan"] == ("True True" if threads == 0 else "False False")
