@@ -54,3 +54,20 @@ def test_euler_f32_sampled_check_states_errors_per_variable():
     assert v["bit_exact"]
     assert set(v["rel_1_vs_binary64"]) == {"rho", "m", "E"}
     assert all(0.0 <= e < 1e-2 for e in v["rel_1_vs_binary64"].values())
+
+
+def test_schedule_follows_the_library_route_rule():
+    """bench.py times heat through one persistent launch exactly where
+    swept_solve takes it: more than 1024 tiles of 1792 cells or more."""
+    def work(eq, n):
+        return wl.Workload(f"{eq}_{n}", eq, n, 10, 0.25, 1.0, 1)
+    assert bench.default_schedule(sw.HEAT_F64, work("heat", 1 << 22)) == "persistent"
+    assert bench.default_schedule(sw.HEAT_F32, work("heat", 1 << 24)) == "persistent"
+    assert bench.default_schedule(sw.HEAT_F64, work("heat", 10_000_000)) == "persistent"  # W 2000
+    assert bench.default_schedule(sw.HEAT_F64, work("heat", 1 << 21)) == "phases"  # 1024 tiles
+    assert bench.default_schedule(sw.HEAT_F64, work("heat", 1 << 20)) == "phases"
+    assert bench.default_schedule(sw.EULER_F64, work("euler", 1 << 24)) == "phases"
+    assert bench.default_schedule(sw.KS_F64, work("ks", 1 << 24)) == "phases"
+    assert not bench.persistent_route(sw.HEAT_F64, 1 << 23, 1024)  # narrow tiles
+    assert bench.persistent_route(sw.HEAT_F64, 1792 * 1025, 1792)
+    assert not bench.persistent_route(sw.HEAT_F64, 1792 * 1024, 1792)
