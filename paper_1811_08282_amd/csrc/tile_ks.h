@@ -15,6 +15,16 @@
 // side) with the two-slot working struct of the heat scheme (slot m & 1
 // holds level m; a neighbour within two cells is at most one level ahead and
 // writes only the slot the cell no longer reads).
+//
+// Level sweep: each thread updates four consecutive cells.  It reads their
+// eight-cell neighbourhood with four 16-byte LDS loads, forms the six second
+// differences s_k and six fluxes f(u_k) between them once (instead of three
+// and two per cell) and writes the four results with two 16-byte stores.
+// Every window is a whole number of such groups and every group starts on an
+// even cell: W is a multiple of 4 (the host's width rule for radius 2) and
+// the margins 2|j - 1| are even, so the windows [m + 2, W - m + 2) of the
+// LDS slots hold a multiple of 4 cells from an even index, and the slots
+// (W + 4 doubles each) start on 32-byte boundaries.
 #pragma once
 
 #include "geom.h"
@@ -23,6 +33,8 @@
 namespace sw {
 
 constexpr int kKsRadius = 2;
+constexpr int kKsCells = 4;  // consecutive cells per thread and level
+static_assert(kKsCells == 4, "the level sweep stores a group as two 16-byte halves");
 
 __host__ __device__ __forceinline__ double ks_second(double l, double m, double r)
 {
@@ -44,9 +56,40 @@ __host__ __device__ __forceinline__ double ks_update(double umm, double um, doub
     return u - ((a * (ks_flux(up) - ks_flux(um)) + b * s0) + c * q);
 }
 
+// One level over the LDS window [lo, hi) (hi - lo a multiple of 4, lo even),
+// from slot src to slot dst; reads [lo - 2, hi + 2).
+template <int NT>
+__device__ __forceinline__ void ks_level(const double *src, double *dst, int lo, int hi, double a,
+                                         double b, double c)
+{
+    for (int x0 = lo + kKsCells * (int)threadIdx.x; x0 < hi; x0 += kKsCells * NT) {
+        double u[kKsCells + 4], sd[kKsCells + 2], fl[kKsCells + 2], out[kKsCells];
+        const double2 *in2 = reinterpret_cast<const double2 *>(src + x0 - 2);
+#pragma unroll
+        for (int k = 0; k < (kKsCells + 4) / 2; ++k) {  // cells x0 - 2 .. x0 + 5
+            const double2 v = in2[k];
+            u[2 * k] = v.x;
+            u[2 * k + 1] = v.y;
+        }
+#pragma unroll
+        for (int k = 0; k < kKsCells + 2; ++k) {  // cells x0 - 1 .. x0 + 4
+            sd[k] = ks_second(u[k], u[k + 1], u[k + 2]);
+            fl[k] = ks_flux(u[k + 1]);
+        }
+        // cell x0 + k: ks_update of u[k .. k + 4] with the shared terms
+#pragma unroll
+        for (int k = 0; k < kKsCells; ++k) {
+            const double q = (sd[k + 2] - sd[k + 1]) + (sd[k] - sd[k + 1]);
+            out[k] = u[k + 2] - ((a * (fl[k + 2] - fl[k]) + b * sd[k + 1]) + c * q);
+        }
+        double2 *out2 = reinterpret_cast<double2 *>(dst + x0);
+        out2[0] = make_double2(out[0], out[1]);
+        out2[1] = make_double2(out[2], out[3]);
+    }
+}
+
 // LDS: s0[w+4], s1[w+4] doubles (LDS index = tile cell + 2).  ws layout:
-// slot0[n], slot1[n].  The level window is swept in LDS with one barrier per
-// level.
+// slot0[n], slot1[n].  One barrier per level.
 template <int NT>
 __device__ __forceinline__ void ks_f64_tile(const TileJob &jb, double *lds, double a, double b,
                                             double c)
@@ -78,8 +121,7 @@ __device__ __forceinline__ void ks_f64_tile(const TileJob &jb, double *lds, doub
         const int64_t lv = jb.base + j;
         const double *src = (lv & 1) ? s0 : s1;
         double *dst = (lv & 1) ? s1 : s0;
-        for (int i = m + R + tid; i < w - m + R; i += NT)
-            dst[i] = ks_update(src[i - 2], src[i - 1], src[i], src[i + 1], src[i + 2], a, b, c);
+        ks_level<NT>(src, dst, m + R, w - m + R, a, b, c);
         __syncthreads();
     }
 
