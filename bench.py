@@ -525,7 +525,7 @@ def persistent_route(eq, n, width):
 
 
 def default_schedule(eq, work):
-    # Euler and Kuramoto-Sivashinsky phases last 8-55 ms: the drain between
+    # Euler and Kuramoto-Sivashinsky phases last 6-55 ms: the drain between
     # launches costs little, and for Euler the two are level or the phase
     # launches win
     width = sw.sw_default_width(eq, work.n)
