@@ -621,15 +621,16 @@ static int autotune_impl(int eq, int64_t n_cells, int64_t probe_steps, sw_stream
     }
     const double dt = 0.1, dx = 1.0;
     // one warm-up solve, then one timed solve: ms per cell-update
-    auto probe = [&](const sw_opts &o, double *per) -> int {
-        int r = swept_solve_ex(eq, n_cells, steps, dt, dx, state, stream, &o);
+    // one warm-up solve, then one timed solve: ms per cell-update
+    auto probe = [&](auto &&solve_once, double *per) -> int {
+        int r = solve_once();
         if (r)
             return r;
         if (hipEventRecord(e0, s) != hipSuccess) {
             (void)hipGetLastError();
             return fail(SW_ERR_HIP, "hipEventRecord failed");
         }
-        r = swept_solve_ex(eq, n_cells, steps, dt, dx, state, stream, &o);
+        r = solve_once();
         if (r)
             return r;
         float ms = 0.f;
@@ -647,16 +648,35 @@ static int autotune_impl(int eq, int64_t n_cells, int64_t probe_steps, sw_stream
         for (int threads = 512; threads >= 64 && rc == SW_OK; threads /= 2) {
             if (threads > 64 && threads / 2 >= w)
                 continue;  // wider workgroups than the tile only idle
-            rc = probe(sw_opts{w, threads, ws, wbytes}, &per);
+            const sw_opts o{w, threads, ws, wbytes};
+            rc = probe([&] { return swept_solve_ex(eq, n_cells, steps, dt, dx, state, stream, &o); },
+                       &per);
             if (rc == SW_OK && per < top.ms_per_update)
                 top = TuneEntry{w, threads, per};
         }
-        // the persistent launch, which swept_solve takes for a width given
-        // with no workgroup size and no workspace (recorded as size 0)
-        if (rc == SW_OK && persistent_route(eq, n_cells, w)) {
-            rc = probe(sw_opts{w, 0, nullptr, 0}, &per);
-            if (rc == SW_OK && per < top.ms_per_update)
-                top = TuneEntry{w, 0, per};
+        // the one persistent launch swept_solve takes at this width (recorded
+        // as workgroup size 0), on working arrays of its own allocated here
+        if (rc == SW_OK && persistent_route(eq, n_cells, w) &&
+            sw::phase_count(steps * substeps(eq), w / 2) >= 2) {
+            sw_problem p{};
+            p.eq = eq;
+            p.width = w;
+            p.n_cells = n_cells;
+            p.n_steps = steps;
+            p.dt = dt;
+            p.dx = dx;
+            p.d_state = state;
+            const size_t pneed = persistent_workspace_bytes(p);
+            void *pws = nullptr;
+            if (pneed && hipMalloc(&pws, pneed) == hipSuccess) {
+                rc = probe([&] { return run_swept_persistent(p, pws, pneed, s); }, &per);
+                (void)hipStreamSynchronize(s);
+                (void)hipFree(pws);
+                if (rc == SW_OK && per < top.ms_per_update)
+                    top = TuneEntry{w, 0, per};
+            } else {
+                (void)hipGetLastError();  // no room: the phase launches stand
+            }
         }
     }
     if (e0)
